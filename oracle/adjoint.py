@@ -1,0 +1,32 @@
+"""Gradients of a linear loss of the Helmholtz solution (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Not in the paper. For x = H^-1 b and L = g . x, with H symmetric:
+  dL/db = lambda, where H lambda = g (the adjoint solve is the same solve),
+  dL/dc = -lambda^T (dH/dc) x for every coefficient c of H.
+In flux form a face coupling K between unknowns i and j enters H as
+K (e_i - e_j)(e_i - e_j)^T, so dL/dK = -(lambda_i - lambda_j)(x_i - x_j), and
+dL/d delta = -lambda * x. With a batch of right-hand sides sharing one
+operator the coefficient gradients are summed over the batch.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .mesh import E, N_
+
+
+def face_gradients(level, lam, x):
+    """Return ``(g_kh[2][nz][ncol], g_kv[nz-1][ncol], g_delta[nz][ncol])``.
+
+    ``lam`` and ``x`` are ``[batch][nz][ncol]`` (or ``[nz][ncol]``).
+    """
+    lam = lam.reshape((-1,) + lam.shape[-2:])
+    x = x.reshape((-1,) + x.shape[-2:])
+    g_kh = np.stack([
+        -((lam - lam[..., level.nbr[d]]) * (x - x[..., level.nbr[d]])).sum(axis=0)
+        for d in (E, N_)])
+    g_kv = -((lam[:, :-1] - lam[:, 1:]) * (x[:, :-1] - x[:, 1:])).sum(axis=0)
+    g_delta = -(lam * x).sum(axis=0)
+    return g_kh, g_kv, g_delta

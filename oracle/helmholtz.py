@@ -1,0 +1,143 @@
+"""The synthetic Helmholtz operator on one level, and its coarse versions (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+The paper's pressure operator H (Eq. helmholtz_operator, Section 3.4) couples
+each cell to its horizontal neighbours and to the cells above and below
+(Section 3.5). Its FE form needs the LFRic model, so a synthetic operator with
+the same structure stands in: a zero-order term delta (the role of H_0 =
+M_3^{Pi*}), one coupling per horizontal face (the role of D_2^h) and one per
+vertical face (the role of D_1^z + D_2^z), in flux form
+
+  (H x)[k,c] = delta[k,c] x[k,c]
+             + sum_{d in E,W,N,S} K_h(face d of c, k) (x[k,c] - x[k,nbr_d(c)])
+             + K_v[k,c]   (x[k,c] - x[k+1,c])   if k < nz-1
+             + K_v[k-1,c] (x[k,c] - x[k-1,c])   if k > 0.
+
+With positive couplings and delta > 0 this is symmetric positive definite
+(a graph Laplacian plus a positive diagonal).
+
+Coarse levels are built by re-discretisation, not by the Galerkin product
+(Section 3.6). Eq. DH_ratios gives how each part scales with the grid: H_0 with
+the cell volume (so the four children's delta add up), the vertical part with
+dx^2 / dz (so the four children's K_v add up), and D_2^h with dz only, not with
+dx (so a coarse horizontal face keeps the average of the two fine faces that
+make it up). Then D_2^h : H_0 drops by 4 per level, as the paper states.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from .mesh import E, W, N_, S
+
+
+def face_coeffs(kh: np.ndarray, ftab: np.ndarray) -> np.ndarray:
+    """Coupling across each of the 4 faces of each column: ``K[d][k][c]``."""
+    nz, ncol = kh.shape[1], kh.shape[2]
+    flat = np.concatenate([kh[0], kh[1]], axis=1)           # [nz][2*ncol]
+    return np.stack([flat[:, ftab[d]] for d in range(4)])   # [4][nz][ncol]
+
+
+def apply(level, kh, kv, delta, x):
+    """y = H x on one level, in flux form. ``x`` is ``[..., nz, ncol]``."""
+    K = face_coeffs(kh, level.ftab)
+    y = delta * x
+    for d in range(4):
+        y = y + K[d] * (x - x[..., :, level.nbr[d]])
+    if x.shape[-2] > 1:
+        dz = x[..., :-1, :] - x[..., 1:, :]
+        flux = kv * dz
+        y[..., :-1, :] += flux
+        y[..., 1:, :] -= flux
+    return y
+
+
+def assemble(level, kh, kv, delta) -> sp.csr_matrix:
+    """Sparse matrix of H, unknown index k*ncol + c (used by the pins)."""
+    nz, ncol = delta.shape
+    n = nz * ncol
+    rows, cols, vals = [], [], []
+    idx = np.arange(n).reshape(nz, ncol)
+    rows.append(idx.ravel()); cols.append(idx.ravel()); vals.append(delta.ravel())
+
+    def couple(i, j, w):
+        rows.extend([i, j, i, j]); cols.extend([i, j, j, i])
+        vals.extend([w, w, -w, -w])
+
+    # each horizontal face once, through the faces a column owns (E and N)
+    for slot, d in ((0, E), (1, N_)):
+        couple(idx.ravel(), idx[:, level.nbr[d]].ravel(), kh[slot].ravel())
+    if nz > 1:
+        couple(idx[:-1].ravel(), idx[1:].ravel(), kv.ravel())
+    A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(n, n))
+    return A.tocsr()
+
+
+def column_tridiagonal(level, kh, kv, delta):
+    """The column operator H_z (Section 3.5) as ``(sub, diag, sup)``, each ``[nz][ncol]``.
+
+    H_z keeps every coupling inside a column and the whole diagonal of H; the
+    horizontal off-diagonal couplings form the rest, H - H_z. For this 7-point
+    operator H_z is already tridiagonal, so the smoother's matrix (H_z with the
+    next-to-nearest vertical couplings dropped) is H_z itself.
+    ``sub[k]`` couples k to k-1 (zero at k = 0), ``sup[k]`` couples k to k+1.
+    """
+    nz, ncol = delta.shape
+    K = face_coeffs(kh, level.ftab)
+    diag = delta + K.sum(axis=0)
+    sub = np.zeros((nz, ncol))
+    sup = np.zeros((nz, ncol))
+    if nz > 1:
+        diag[:-1] += kv
+        diag[1:] += kv
+        sup[:-1] = -kv
+        sub[1:] = -kv
+    return sub, diag, sup
+
+
+def coarsen(kh, kv, delta, childs):
+    """Coefficients on the next coarser level by re-discretisation (Section 3.6).
+
+    ``childs[s][C]`` lists the fine children (di, dj) = (0,0), (1,0), (0,1),
+    (1,1) of coarse column C. The coarse E face is made of the E faces of the
+    children with di = 1, the coarse N face of the N faces of those with dj = 1.
+    """
+    c00, c10, c01, c11 = childs
+    kh_c = np.stack([0.5 * (kh[0][:, c10] + kh[0][:, c11]),
+                     0.5 * (kh[1][:, c01] + kh[1][:, c11])])
+    kv_c = ((kv[:, c00] + kv[:, c10]) + kv[:, c01]) + kv[:, c11]
+    delta_c = ((delta[:, c00] + delta[:, c10]) + delta[:, c01]) + delta[:, c11]
+    return kh_c, kv_c, delta_c
+
+
+class Hierarchy:
+    """All multigrid levels of one operator: tables and coefficients per level."""
+
+    def __init__(self, levels, parents, childs, kh, kv, delta, dtype=np.float64):
+        self.levels, self.parents, self.childs = levels, parents, childs
+        self.coeffs = [(kh, kv, delta)]
+        for l in range(len(levels) - 1):
+            self.coeffs.append(coarsen(*self.coeffs[-1], childs[l]))
+        self.dtype = np.dtype(dtype)
+        if self.dtype != np.float64:
+            # coarse coefficients are made in float64 and rounded once
+            self.coeffs = [tuple(a.astype(dtype) for a in c) for c in self.coeffs]
+
+    @property
+    def nlevels(self):
+        return len(self.levels)
+
+    def apply(self, l, x):
+        return apply(self.levels[l], *self.coeffs[l], x)
+
+    def column_tridiagonal(self, l):
+        return column_tridiagonal(self.levels[l], *self.coeffs[l])
+
+    def astype(self, dtype):
+        h = Hierarchy.__new__(Hierarchy)
+        h.levels, h.parents, h.childs = self.levels, self.parents, self.childs
+        h.dtype = np.dtype(dtype)
+        h.coeffs = [tuple(a.astype(dtype) for a in c) for c in self.coeffs]
+        return h

@@ -1,0 +1,88 @@
+"""Preconditioned conjugate gradients around the V-cycle (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Section 4.1 lists CG(A, P, eps) among the Krylov solvers that take a linear
+operator A and a preconditioner P; the preconditioner here is one V-cycle from
+a zero guess (Section 3.6), or, with one level, block-Jacobi sweeps
+(P_H^(Jac)). The synthetic operator is symmetric positive definite and so is
+the V-cycle with equal pre- and post-smoothing, so CG applies. Convergence is
+judged on the recursively updated residual, ||r|| <= rtol ||b||, from x = 0.
+
+The float32 form keeps the outer loop in float64 and runs only the
+preconditioner in float32 (its input rounded from float64, its coefficients
+built in float64 and rounded once); its output is widened back to float64.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from .multigrid import MGParams, vcycle
+
+
+@dataclasses.dataclass
+class CGResult:
+    x: np.ndarray
+    iters: int
+    relres: float
+    converged: bool
+    history: list
+
+
+def pcg(apply_A, apply_M, b, rtol=1e-8, maxiter=200, flexible=False) -> CGResult:
+    """Hestenes-Stiefel PCG; ``flexible`` uses the Polak-Ribiere beta.
+
+    ``iters`` counts applications of A inside the loop.
+    """
+    x = np.zeros_like(b)
+    bnorm = float(np.linalg.norm(b))
+    if bnorm == 0.0:
+        return CGResult(x, 0, 0.0, True, [0.0])
+    r = b.copy()
+    z = apply_M(r)
+    p = z.copy()
+    rho = float(np.vdot(r, z))
+    hist = [1.0]
+    it = 0
+    while True:
+        q = apply_A(p)
+        alpha = rho / float(np.vdot(p, q))
+        x = x + alpha * p
+        r_old = r
+        r = r - alpha * q
+        it += 1
+        rel = float(np.linalg.norm(r)) / bnorm
+        hist.append(rel)
+        if rel <= rtol:
+            return CGResult(x, it, rel, True, hist)
+        if it >= maxiter:
+            return CGResult(x, it, rel, False, hist)
+        z = apply_M(r)
+        rho_new = float(np.vdot(r, z))
+        if flexible:
+            beta = float(np.vdot(z, r - r_old)) / rho
+        else:
+            beta = rho_new / rho
+        p = z + beta * p
+        rho = rho_new
+
+
+def mg_preconditioner(hier, params: MGParams = MGParams()):
+    """x = M r: one V-cycle from zero on ``hier`` (float64)."""
+    return lambda r: vcycle(hier, r, params)
+
+
+def mg_preconditioner_f32(hier, params: MGParams = MGParams()):
+    """Float32 V-cycle used inside the float64 loop (input rounded, output widened)."""
+    h32 = hier.astype(np.float32)
+    return lambda r: vcycle(h32, r.astype(np.float32), params).astype(np.float64)
+
+
+def solve(hier, b, rtol=1e-8, maxiter=200, params: MGParams = MGParams(),
+          precision="fp64", flexible=False) -> CGResult:
+    """MG-preconditioned CG for H x = b on the finest level of ``hier``."""
+    M = mg_preconditioner_f32(hier, params) if precision == "fp32" else \
+        mg_preconditioner(hier, params)
+    return pcg(lambda v: hier.apply(0, v), M, b, rtol, maxiter, flexible)
