@@ -1,0 +1,168 @@
+/*
+ * helmholtz.h - C ABI of the MI355X (gfx950) Helmholtz multigrid library.
+ *
+ * The library solves H x = b for the pressure-correction (Helmholtz) operator
+ * of a semi-implicit atmospheric model on a cubed-sphere mesh of vertical
+ * columns, preconditioned by the tensor-product multigrid V-cycle of
+ * Maynard, Melvin and Mueller (Section 3.6 of their paper): block-Jacobi
+ * smoothing with exact tridiagonal solves in each column (Eq. jacobi),
+ * horizontal-only 2x2 coarsening, prolongation by natural injection,
+ * restriction as its dual, and a few smoothing sweeps instead of a coarse
+ * solve (Algorithm 1). The Krylov loop is conjugate gradients (Section 4.1).
+ *
+ * Operator. H is a symmetric positive definite face-coupling operator that
+ * stands in for the paper's finite-element H (Eq. helmholtz_operator):
+ *   (H x)[k,c] = delta[k,c] x[k,c]
+ *              + sum over the 4 horizontal faces f of c: K_h(f,k) (x[k,c] - x[k,nbr_f(c)])
+ *              + kv[k,c]   (x[k,c] - x[k+1,c])   (k < nz-1)
+ *              + kv[k-1,c] (x[k,c] - x[k-1,c])   (k > 0).
+ * Coarse operators are re-discretised (Section 3.6, scalings of Eq. DH_ratios):
+ * a coarse horizontal face takes the mean of its two fine faces, the coarse
+ * kv and delta the sum over the four children.
+ *
+ * Mesh. C<N>: 6 panels of N x N columns, column index c = p*N*N + j*N + i.
+ * Directions E=0 (+i), W=1, N=2 (+j), S=3. Panel orientation (normal, E axis,
+ * N axis) on the cube: p0 (+x,+y,+z), p1 (+y,-x,+z), p2 (-x,-z,-y),
+ * p3 (-y,-z,+x), p4 (+z,-x,-y), p5 (-z,+y,+x). Each horizontal face is stored
+ * once, as the E face (slot 0) or the N face (slot 1) of one of its cells.
+ * Level l = 1..L has N / 2^(l-1) columns per panel edge; coarse column of
+ * (p,i,j) is (p,i/2,j/2).
+ *
+ * Layouts. Coefficients: kh[2][nz][ncol], kv[nz-1][ncol], delta[nz][ncol].
+ * Vectors: [batch][nz][ncol], contiguous, column index fastest, float64
+ * unless the name says f32. All array pointers are DEVICE pointers unless
+ * marked "host". Every call is ordered on the given HIP stream.
+ *
+ * Memory. The library never allocates device memory: the caller passes one
+ * workspace of helmholtz_workspace_bytes(cfg) bytes to helmholtz_create and
+ * keeps it alive until helmholtz_destroy. The handle itself lives in host
+ * memory (plus a small pinned host buffer for the solver's scalars).
+ * Calls on one handle must not overlap (a handle is not thread-safe and its
+ * workspace is shared by all its calls).
+ *
+ * Errors. Functions return HELMHOLTZ_OK (0) or a negative code;
+ * helmholtz_solve may also return HELMHOLTZ_NOT_CONVERGED (1), in which case
+ * its outputs are still valid. helmholtz_strerror(code) names the code.
+ */
+#ifndef HELMHOLTZ_H
+#define HELMHOLTZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct helmholtz_s* helmholtz_t;
+typedef struct ihipStream_t* helmholtz_stream_t; /* a hipStream_t; NULL = default stream */
+
+enum {
+    HELMHOLTZ_OK = 0,
+    HELMHOLTZ_NOT_CONVERGED = 1, /* solve hit maxiter; outputs valid              */
+    HELMHOLTZ_EINVAL = -1,       /* bad argument, config or coefficient value      */
+    HELMHOLTZ_ESHAPE = -2,       /* N % 2^(L-1) != 0, nz > HELMHOLTZ_NZ_MAX, batch
+                                    > max_batch, or sizes beyond 32-bit indexing   */
+    HELMHOLTZ_EWORKSPACE = -3,   /* workspace NULL, too small or misaligned        */
+    HELMHOLTZ_ENONFINITE = -4,   /* NaN/Inf in coefficients or in a solve          */
+    HELMHOLTZ_EHIP = -5          /* a HIP runtime call or kernel launch failed     */
+};
+
+enum { HELMHOLTZ_FP64 = 0, HELMHOLTZ_FP32 = 1 };               /* V-cycle precision   */
+enum { HELMHOLTZ_CG_STANDARD = 0, HELMHOLTZ_CG_FLEXIBLE = 1 };  /* beta of the CG loop */
+
+#define HELMHOLTZ_NZ_MAX 128
+#define HELMHOLTZ_WORKSPACE_ALIGN 256
+
+typedef struct {
+    int32_t N;            /* columns per panel edge on the finest level, >= 1             */
+    int32_t nz;           /* vertical levels, 1 .. HELMHOLTZ_NZ_MAX                         */
+    int32_t nlevels;      /* multigrid levels L >= 1; N must be divisible by 2^(L-1)        */
+    int32_t n_pre;        /* pre-smoothing sweeps (>= 0), Algorithm 1                        */
+    int32_t n_post;       /* post-smoothing sweeps (>= 0)                                    */
+    int32_t n_coarse;     /* sweeps on the coarsest level (>= 1)                             */
+    double omega;         /* over-relaxation of Eq. jacobi, 0 < omega <= 1.5                 */
+    int32_t mg_precision; /* HELMHOLTZ_FP64 or HELMHOLTZ_FP32 (V-cycle arithmetic)           */
+    int32_t cg_variant;   /* HELMHOLTZ_CG_STANDARD or HELMHOLTZ_CG_FLEXIBLE                  */
+    int32_t max_batch;    /* largest batch any call will pass, >= 1                          */
+} helmholtz_config;
+
+/* Bytes of device workspace that helmholtz_create needs for cfg; 0 if cfg is
+ * invalid. Pure host function, no HIP calls. */
+size_t helmholtz_workspace_bytes(const helmholtz_config* cfg);
+
+/* Build the operator hierarchy (Section 3.6): mesh tables of every level,
+ * coarse coefficients by re-discretisation, the column factorisations used by
+ * the smoother (the LU factors of the column operator that the block-Jacobi
+ * step needs) and float32 copies of all of them.
+ *   kh    [2][nz][ncol] coupling across each column's E (slot 0) and N (slot 1) face, >= 0
+ *   kv    [nz-1][ncol]  coupling between levels k and k+1 (may be NULL if nz == 1), >= 0
+ *   delta [nz][ncol]    zero-order term, > 0
+ *   workspace           device buffer of >= helmholtz_workspace_bytes(cfg) bytes,
+ *                       HELMHOLTZ_WORKSPACE_ALIGN-aligned, owned by the caller
+ * The coefficients are copied; the caller may free them when this returns.
+ * Synchronises `stream` once. On success *out holds a new handle. */
+int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double* kv,
+                     const double* delta, void* workspace, size_t workspace_bytes,
+                     helmholtz_stream_t stream, helmholtz_t* out);
+
+/* Release host state (handle, pinned scalars). Never touches the workspace. */
+int helmholtz_destroy(helmholtz_t h);
+
+/* y = H x on the finest level (the operator of Eq. helmholtz), float64,
+ * x and y [batch][nz][ncol], must not overlap. Asynchronous. */
+int helmholtz_apply(helmholtz_t h, const double* x, double* y, int32_t batch,
+                    helmholtz_stream_t stream);
+
+/* x = M b: one V-cycle of Algorithm 1 from a zero initial guess, in the
+ * handle's mg_precision (float32 V-cycles round b once and widen x once).
+ * b and x [batch][nz][ncol] float64, must not overlap. Asynchronous. */
+int helmholtz_vcycle(helmholtz_t h, const double* b, double* x, int32_t batch,
+                     helmholtz_stream_t stream);
+
+/* Same V-cycle entirely in float32 (coefficients, vectors and accumulation).
+ * b and x [batch][nz][ncol] float32, must not overlap. Asynchronous. */
+int helmholtz_vcycle_f32(helmholtz_t h, const float* b, float* x, int32_t batch,
+                         helmholtz_stream_t stream);
+
+/* Solve H x = b by conjugate gradients (Section 4.1) preconditioned by one
+ * V-cycle per iteration, from x = 0, independently for each right-hand side.
+ * The outer loop (residual update, dot products, norms, solution update) is
+ * float64; the V-cycle runs in mg_precision.
+ *   rtol     stop when ||r||_2 <= rtol ||b||_2 (recursively updated residual)
+ *   maxiter  largest number of iterations (applications of H), >= 1
+ *   iters    host [batch]: iterations taken per right-hand side (may be NULL)
+ *   relres   host [batch]: final ||r||_2 / ||b||_2 (0 when b = 0) (may be NULL)
+ * Synchronises `stream` once per iteration for the convergence test.
+ * Returns HELMHOLTZ_NOT_CONVERGED if any right-hand side hit maxiter and
+ * HELMHOLTZ_ENONFINITE if b or a residual norm is not finite. */
+int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, double rtol,
+                    int32_t maxiter, int32_t* iters, double* relres,
+                    helmholtz_stream_t stream);
+
+/* Gradients of L = sum_b g_b . x_b with respect to the operator's
+ * coefficients, given x = H^-1 b and the adjoint lam = H^-1 g (H is
+ * symmetric, so the adjoint solve is helmholtz_solve on g):
+ *   g_kh[s][k][c] = -sum_b (lam[k,c]-lam[k,n]) (x[k,c]-x[k,n]), n the E (s=0) or N (s=1) neighbour
+ *   g_kv[k][c]    = -sum_b (lam[k,c]-lam[k+1,c]) (x[k,c]-x[k+1,c])
+ *   g_delta[k][c] = -sum_b lam[k,c] x[k,c]
+ * lam, x [batch][nz][ncol]; outputs are overwritten (g_kv may be NULL if nz == 1).
+ * Asynchronous. */
+int helmholtz_face_grad(helmholtz_t h, const double* lam, const double* x, int32_t batch,
+                        double* g_kh, double* g_kv, double* g_delta, helmholtz_stream_t stream);
+
+/* Mesh tables of C<N> as built by the library (host arrays, int32):
+ *   nbr    [4][6N^2]  neighbour column in directions E, W, N, S
+ *   ftab   [4][6N^2]  stored face of each direction: slot*ncol + owner column
+ *   parent [6N^2]     column of C<N/2> that contains each column (NULL, or ignored if N is odd)
+ * Pure host function. */
+int helmholtz_mesh_tables(int32_t N, int32_t* nbr, int32_t* ftab, int32_t* parent);
+
+/* Static description of a return code. */
+const char* helmholtz_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HELMHOLTZ_H */

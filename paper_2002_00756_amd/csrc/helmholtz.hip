@@ -1,0 +1,653 @@
+// Host side of the C ABI declared in include/helmholtz.h: workspace layout,
+// operator set-up, the V-cycle of Algorithm 1 and the conjugate-gradient
+// loop, all as stream-ordered launches of the kernels in kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/helmholtz.h"
+#include "kernels.hpp"
+#include "mesh.hpp"
+
+using namespace hh;
+
+namespace {
+
+constexpr int kRedBlocks = 512;  // partial sums per right-hand side for vector reductions
+constexpr int kApplyChunk = 8;   // vertical levels per thread in apply / residual kernels
+
+template <typename T>
+struct LevelData {
+    T* kh = nullptr;  // [nz][2][ncol]
+    T* kv = nullptr;  // [nz][ncol]
+    T* dl = nullptr;  // [nz][ncol]
+    T* cc = nullptr;  // [nz][ncol]
+    T* mm = nullptr;  // [nz][ncol]
+    T* b = nullptr;   // [B][nz][ncol]   level >= 1 (and level 0 for float32)
+    T* x = nullptr;   // [B][nz][ncol]   level >= 1 (and level 0 for float32)
+    T* t = nullptr;   // [B][nz][ncol]   ping-pong partner of x
+};
+
+struct Level {
+    int N = 0;
+    int ncol = 0;
+    int32_t* nbr = nullptr;     // [4][ncol]
+    int32_t* fface = nullptr;   // [2][ncol]
+    int32_t* parent = nullptr;  // [ncol] into level + 1 (not on the coarsest)
+    int32_t* child = nullptr;   // [4][ncol] into level - 1 (not on the finest)
+    LevelData<double> d;
+    LevelData<float> f;
+};
+
+// Bump allocator over the caller's workspace; run with base 0 to size it.
+struct Carver {
+    uintptr_t base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + HELMHOLTZ_WORKSPACE_ALIGN - 1) / HELMHOLTZ_WORKSPACE_ALIGN *
+              HELMHOLTZ_WORKSPACE_ALIGN;
+        T* p = reinterpret_cast<T*>(base + off);
+        off += count * sizeof(T);
+        return p;
+    }
+};
+
+bool config_ok(const helmholtz_config* c) {
+    if (!c) return false;
+    if (c->N < 1 || c->nz < 1 || c->nz > HELMHOLTZ_NZ_MAX || c->nlevels < 1 || c->nlevels > 20)
+        return false;
+    if (c->n_pre < 0 || c->n_post < 0 || c->n_coarse < 1) return false;
+    if (!(c->omega > 0.0 && c->omega <= 1.5)) return false;
+    if (c->mg_precision != HELMHOLTZ_FP64 && c->mg_precision != HELMHOLTZ_FP32) return false;
+    if (c->cg_variant != HELMHOLTZ_CG_STANDARD && c->cg_variant != HELMHOLTZ_CG_FLEXIBLE)
+        return false;
+    if (c->max_batch < 1) return false;
+    return true;
+}
+
+int shape_error(const helmholtz_config* c) {
+    if (c->N % (1 << (c->nlevels - 1)) != 0) return HELMHOLTZ_ESHAPE;
+    const int64_t ncol = 6 * int64_t(c->N) * c->N;
+    // tables and face indices are 32-bit; batch offsets are 64-bit
+    if (2 * ncol >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
+    if (int64_t(c->nz) * ncol >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
+    return HELMHOLTZ_OK;
+}
+
+}  // namespace
+
+struct helmholtz_s {
+    helmholtz_config cfg{};
+    int L = 0, nz = 0, B = 0;
+    int64_t n = 0;  // unknowns per right-hand side on the finest level
+    std::vector<Level> lev;
+    // Krylov vectors [B][n]
+    double* r = nullptr;
+    double* p = nullptr;
+    double* q = nullptr;
+    double* z = nullptr;  // float64 preconditioned residual (float64 V-cycle)
+    double* partial = nullptr;
+    double* partial2 = nullptr;
+    int pstride = 0;
+    double* sc = nullptr;  // [B][8] scalars
+    int* active = nullptr; // [B]
+    int* flags = nullptr;  // set-up validation bits
+    // pinned host mirror of sc + active + flags
+    double* hsc = nullptr;
+    int* hact = nullptr;
+    int* hflags = nullptr;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+void layout(helmholtz_s* h, Carver& cv) {
+    const int nz = h->nz, B = h->B;
+    for (int l = 0; l < h->L; ++l) {
+        Level& v = h->lev[l];
+        const size_t nc = size_t(v.ncol);
+        const size_t nv = size_t(nz) * nc;
+        v.nbr = cv.take<int32_t>(4 * nc);
+        v.fface = cv.take<int32_t>(2 * nc);
+        v.parent = (l + 1 < h->L) ? cv.take<int32_t>(nc) : nullptr;
+        v.child = (l > 0) ? cv.take<int32_t>(4 * nc) : nullptr;
+        v.d.kh = cv.take<double>(2 * nv);
+        v.d.kv = cv.take<double>(nv);
+        v.d.dl = cv.take<double>(nv);
+        v.d.cc = cv.take<double>(nv);
+        v.d.mm = cv.take<double>(nv);
+        // float32 copies: contiguous in the same order, so one conversion per level
+        v.f.kh = cv.take<float>(6 * nv);
+        v.f.kv = v.f.kh + 2 * nv;
+        v.f.dl = v.f.kh + 3 * nv;
+        v.f.cc = v.f.kh + 4 * nv;
+        v.f.mm = v.f.kh + 5 * nv;
+        if (l > 0) {
+            v.d.b = cv.take<double>(size_t(B) * nv);
+            v.d.x = cv.take<double>(size_t(B) * nv);
+        }
+        v.d.t = cv.take<double>(size_t(B) * nv);
+        v.f.b = cv.take<float>(size_t(B) * nv);
+        v.f.x = cv.take<float>(size_t(B) * nv);
+        v.f.t = cv.take<float>(size_t(B) * nv);
+    }
+    const size_t nb = size_t(B) * size_t(h->n);
+    h->r = cv.take<double>(nb);
+    h->p = cv.take<double>(nb);
+    h->q = cv.take<double>(nb);
+    h->z = cv.take<double>(nb);
+    const int ntile0 = (h->lev[0].ncol + kBlock - 1) / kBlock;
+    const int nkc0 = (nz + kApplyChunk - 1) / kApplyChunk;
+    h->pstride = std::max(kRedBlocks, ntile0 * nkc0);
+    h->partial = cv.take<double>(size_t(B) * h->pstride);
+    h->partial2 = cv.take<double>(size_t(B) * h->pstride);
+    h->sc = cv.take<double>(size_t(B) * 8);
+    h->active = cv.take<int>(size_t(B));
+    h->flags = cv.take<int>(4);
+}
+
+void init_shape(helmholtz_s* h, const helmholtz_config* cfg) {
+    h->cfg = *cfg;
+    h->L = cfg->nlevels;
+    h->nz = cfg->nz;
+    h->B = cfg->max_batch;
+    h->lev.assign(h->L, Level{});
+    for (int l = 0; l < h->L; ++l) {
+        h->lev[l].N = cfg->N >> l;
+        h->lev[l].ncol = 6 * h->lev[l].N * h->lev[l].N;
+    }
+    h->n = int64_t(cfg->nz) * h->lev[0].ncol;
+}
+
+inline int grid_for(int64_t n) {
+    return int(std::min<int64_t>((n + kBlock - 1) / kBlock, 65536));
+}
+
+#define HH_CHECK(expr)                                   \
+    do {                                                 \
+        if ((expr) != hipSuccess) return HELMHOLTZ_EHIP; \
+    } while (0)
+
+inline int last_error() { return hipGetLastError() == hipSuccess ? HELMHOLTZ_OK : HELMHOLTZ_EHIP; }
+
+template <typename T>
+LevelView<T> view(const helmholtz_s* h, int l) {
+    const Level& v = h->lev[l];
+    const LevelData<T>& d = [&]() -> const LevelData<T>& {
+        if constexpr (std::is_same<T, double>::value) return v.d;
+        else return v.f;
+    }();
+    return LevelView<T>{v.ncol, h->nz, v.nbr, v.fface, d.kh, d.kv, d.dl, d.cc, d.mm};
+}
+
+template <typename T>
+LevelData<T>& data(helmholtz_s* h, int l) {
+    if constexpr (std::is_same<T, double>::value) return h->lev[l].d;
+    else return h->lev[l].f;
+}
+
+// ---- sweep launch: compile-time column length bucket --------------------
+template <typename T, int NZMAX, int MODE>
+void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
+                    int batch, const int* active, hipStream_t s) {
+    const Level& v = h->lev[l];
+    const int ntile = (v.ncol + kBlock - 1) / kBlock;
+    const int32_t* par = (l + 1 < h->L) ? v.parent : nullptr;
+    const int ncol_c = (l + 1 < h->L) ? h->lev[l + 1].ncol : 0;
+    hipLaunchKernelGGL((k_sweep<T, NZMAX, MODE>), dim3(ntile * batch), dim3(kBlock), 0, s,
+                       view<T>(h, l), b, x, xc, par, ncol_c, y, T(h->cfg.omega), batch, active);
+}
+
+template <typename T, int MODE>
+void launch_sweep_m(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
+                    int batch, const int* active, hipStream_t s) {
+    const int nz = h->nz;
+#define HH_SWEEP_BUCKET(NZB)                                                     \
+    if (nz <= NZB) {                                                             \
+        launch_sweep_b<T, NZB, MODE>(h, l, b, x, xc, y, batch, active, s);       \
+        return;                                                                  \
+    }
+    HH_SWEEP_BUCKET(8)
+    HH_SWEEP_BUCKET(16)
+    HH_SWEEP_BUCKET(32)
+    HH_SWEEP_BUCKET(48)
+    HH_SWEEP_BUCKET(72)
+    HH_SWEEP_BUCKET(96)
+    HH_SWEEP_BUCKET(128)
+#undef HH_SWEEP_BUCKET
+}
+
+template <typename T>
+void launch_sweep(const helmholtz_s* h, int l, int mode, const T* b, const T* x, const T* xc,
+                  T* y, int batch, const int* active, hipStream_t s) {
+    switch (mode) {
+        case kZero: launch_sweep_m<T, kZero>(h, l, b, x, xc, y, batch, active, s); break;
+        case kPlain: launch_sweep_m<T, kPlain>(h, l, b, x, xc, y, batch, active, s); break;
+        case kProlong: launch_sweep_m<T, kProlong>(h, l, b, x, xc, y, batch, active, s); break;
+        default: launch_sweep_m<T, kProlongZero>(h, l, b, x, xc, y, batch, active, s); break;
+    }
+}
+
+template <typename T>
+void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, T* bc, int batch,
+                           const int* active, hipStream_t s) {
+    const Level& c = h->lev[l + 1];
+    const int ntile = (c.ncol + kBlock - 1) / kBlock;
+    const int nkc = (h->nz + kApplyChunk - 1) / kApplyChunk;
+    const dim3 grid(ntile * nkc * batch);
+    if (x)
+        hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, dim3(kBlock), 0, s, view<T>(h, l),
+                           c.child, c.ncol, b, x, bc, batch, kApplyChunk, nkc, active);
+    else
+        hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, dim3(kBlock), 0, s, view<T>(h, l),
+                           c.child, c.ncol, b, x, bc, batch, kApplyChunk, nkc, active);
+}
+
+template <typename T>
+void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, bool dot,
+                  const int* active, hipStream_t s) {
+    const Level& v = h->lev[l];
+    const int ntile = (v.ncol + kBlock - 1) / kBlock;
+    const int nkc = (h->nz + kApplyChunk - 1) / kApplyChunk;
+    const dim3 grid(ntile * nkc * batch);
+    if (dot)
+        hipLaunchKernelGGL((k_apply<T, true>), grid, dim3(kBlock), 0, s, view<T>(h, l), x, y,
+                           batch, kApplyChunk, nkc, h->partial, h->pstride, active);
+    else
+        hipLaunchKernelGGL((k_apply<T, false>), grid, dim3(kBlock), 0, s, view<T>(h, l), x, y,
+                           batch, kApplyChunk, nkc, nullptr, 0, active);
+}
+
+// ---- V-cycle (Algorithm 1) ------------------------------------------------
+// Level l smooths b_l into out_l, using tmp_l as the Jacobi ping-pong partner.
+// The writes of x on one level alternate between the two buffers; they are
+// assigned from the last write backwards so that the last lands in out_l.
+template <typename T>
+void vcycle_level(helmholtz_s* h, int l, const T* b, T* out, int batch, const int* active,
+                  hipStream_t s) {
+    const helmholtz_config& cfg = h->cfg;
+    T* tmp = data<T>(h, l).t;
+    const bool coarsest = (l == h->L - 1);
+    if (coarsest) {
+        const int W = cfg.n_coarse;
+        const T* prev = nullptr;
+        for (int j = 0; j < W; ++j) {
+            T* dst = ((W - 1 - j) % 2 == 0) ? out : tmp;
+            launch_sweep<T>(h, l, j == 0 ? kZero : kPlain, b, prev, nullptr, dst, batch, active, s);
+            prev = dst;
+        }
+        return;
+    }
+    const int W = cfg.n_pre + std::max(cfg.n_post, 1);
+    int j = 0;
+    const T* prev = nullptr;
+    auto dst_of = [&](int jj) { return ((W - 1 - jj) % 2 == 0) ? out : tmp; };
+    for (int i = 0; i < cfg.n_pre; ++i, ++j) {
+        T* dst = dst_of(j);
+        launch_sweep<T>(h, l, j == 0 ? kZero : kPlain, b, prev, nullptr, dst, batch, active, s);
+        prev = dst;
+    }
+    LevelData<T>& c = data<T>(h, l + 1);
+    launch_resid_restrict<T>(h, l, b, prev, c.b, batch, active, s);
+    vcycle_level<T>(h, l + 1, c.b, c.x, batch, active, s);
+    if (cfg.n_post == 0) {
+        T* dst = dst_of(j);
+        const Level& v = h->lev[l];
+        const int64_t total = int64_t(batch) * h->nz * v.ncol;
+        hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(total)), dim3(kBlock), 0, s, v.ncol,
+                           h->nz, h->lev[l + 1].ncol, v.parent, prev, c.x, dst, total);
+        return;
+    }
+    for (int i = 0; i < cfg.n_post; ++i, ++j) {
+        T* dst = dst_of(j);
+        int mode = kPlain;
+        if (i == 0) mode = prev ? kProlong : kProlongZero;
+        launch_sweep<T>(h, l, mode, b, prev, c.x, dst, batch, active, s);
+        prev = dst;
+    }
+}
+
+int check_batch(const helmholtz_s* h, int32_t batch) {
+    if (!h) return HELMHOLTZ_EINVAL;
+    if (batch < 1 || batch > h->B) return HELMHOLTZ_ESHAPE;
+    return HELMHOLTZ_OK;
+}
+
+template <typename S, typename D>
+void convert(const S* src, D* dst, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL((k_convert<S, D>), dim3(grid_for(n)), dim3(kBlock), 0, s, src, dst, n);
+}
+
+// z = M r on the finest level in the handle's precision; r32/z32 are the
+// float32 level-0 buffers (already holding float(r) when called from solve).
+int precondition(helmholtz_s* h, const double* r, double* z, int batch, bool r32_ready,
+                 const int* active, hipStream_t s) {
+    if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
+        vcycle_level<double>(h, 0, r, z, batch, active, s);
+    } else {
+        LevelData<float>& f = h->lev[0].f;
+        const int64_t n = int64_t(batch) * h->n;
+        if (!r32_ready) convert<double, float>(r, f.b, n, s);
+        vcycle_level<float>(h, 0, f.b, f.x, batch, active, s);
+        if (z) convert<float, double>(f.x, z, n, s);
+    }
+    return last_error();
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+size_t helmholtz_workspace_bytes(const helmholtz_config* cfg) {
+    if (!config_ok(cfg) || shape_error(cfg) != HELMHOLTZ_OK) return 0;
+    helmholtz_s tmp;
+    init_shape(&tmp, cfg);
+    Carver cv{0};
+    layout(&tmp, cv);
+    return cv.off;
+}
+
+const char* helmholtz_strerror(int code) {
+    switch (code) {
+        case HELMHOLTZ_OK: return "ok";
+        case HELMHOLTZ_NOT_CONVERGED: return "solve reached maxiter before rtol";
+        case HELMHOLTZ_EINVAL: return "invalid argument, configuration or coefficient";
+        case HELMHOLTZ_ESHAPE: return "invalid shape (N, nz, levels or batch)";
+        case HELMHOLTZ_EWORKSPACE: return "workspace missing, too small or misaligned";
+        case HELMHOLTZ_ENONFINITE: return "non-finite value (NaN or Inf)";
+        case HELMHOLTZ_EHIP: return "HIP runtime error";
+        default: return "unknown error code";
+    }
+}
+
+int helmholtz_mesh_tables(int32_t N, int32_t* nbr, int32_t* ftab, int32_t* parent) {
+    if (N < 1 || !nbr || !ftab) return HELMHOLTZ_EINVAL;
+    if (2 * 6 * int64_t(N) * N >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
+    build_neighbours(N, nbr);
+    build_face_table(N, nbr, ftab);
+    if (parent && N % 2 == 0) build_parent(N, parent);
+    return HELMHOLTZ_OK;
+}
+
+int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double* kv,
+                     const double* delta, void* workspace, size_t workspace_bytes,
+                     helmholtz_stream_t stream_, helmholtz_t* out) {
+    if (!out) return HELMHOLTZ_EINVAL;
+    *out = nullptr;
+    if (!config_ok(cfg)) return HELMHOLTZ_EINVAL;
+    if (int e = shape_error(cfg)) return e;
+    if (!kh || !delta || (cfg->nz > 1 && !kv)) return HELMHOLTZ_EINVAL;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % HELMHOLTZ_WORKSPACE_ALIGN))
+        return HELMHOLTZ_EWORKSPACE;
+    const size_t need = helmholtz_workspace_bytes(cfg);
+    if (workspace_bytes < need) return HELMHOLTZ_EWORKSPACE;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+
+    helmholtz_s* h = new (std::nothrow) helmholtz_s;
+    if (!h) return HELMHOLTZ_EINVAL;
+    init_shape(h, cfg);
+    Carver cv{reinterpret_cast<uintptr_t>(workspace)};
+    layout(h, cv);
+    h->ws_bytes = need;
+    auto fail = [&](int code) {
+        helmholtz_destroy(h);
+        return code;
+    };
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->hsc), size_t(h->B) * 8 * sizeof(double) +
+                                                             size_t(h->B) * sizeof(int) + 16,
+                      hipHostMallocDefault) != hipSuccess) {
+        h->hsc = nullptr;
+        return fail(HELMHOLTZ_EHIP);
+    }
+    h->hact = reinterpret_cast<int*>(h->hsc + size_t(h->B) * 8);
+    h->hflags = h->hact + h->B;
+
+    // mesh tables of every level, built on the host and copied once
+    const int nz = h->nz;
+    std::vector<int32_t> tab;
+    for (int l = 0; l < h->L; ++l) {
+        Level& v = h->lev[l];
+        const size_t nc = size_t(v.ncol);
+        tab.assign(4 * nc, 0);
+        build_neighbours(v.N, tab.data());
+        std::vector<int32_t> ft(4 * nc);
+        build_face_table(v.N, tab.data(), ft.data());
+        if (hipMemcpyAsync(v.nbr, tab.data(), 4 * nc * sizeof(int32_t), hipMemcpyHostToDevice, s) !=
+            hipSuccess)
+            return fail(HELMHOLTZ_EHIP);
+        std::vector<int32_t> ff(2 * nc);
+        std::copy(ft.begin() + nc, ft.begin() + 2 * nc, ff.begin());       // W
+        std::copy(ft.begin() + 3 * nc, ft.begin() + 4 * nc, ff.begin() + nc);  // S
+        if (hipMemcpyAsync(v.fface, ff.data(), 2 * nc * sizeof(int32_t), hipMemcpyHostToDevice,
+                           s) != hipSuccess)
+            return fail(HELMHOLTZ_EHIP);
+        if (v.parent) {
+            std::vector<int32_t> par(nc);
+            build_parent(v.N, par.data());
+            if (hipMemcpyAsync(v.parent, par.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice,
+                               s) != hipSuccess)
+                return fail(HELMHOLTZ_EHIP);
+        }
+        if (v.child) {
+            std::vector<int32_t> ch(4 * nc);
+            build_children(v.N, ch.data());
+            if (hipMemcpyAsync(v.child, ch.data(), 4 * nc * sizeof(int32_t), hipMemcpyHostToDevice,
+                               s) != hipSuccess)
+                return fail(HELMHOLTZ_EHIP);
+        }
+        // the host vectors must stay alive until the copies have run
+        if (hipStreamSynchronize(s) != hipSuccess) return fail(HELMHOLTZ_EHIP);
+    }
+
+    // coefficients: finest level from the caller, coarser by re-discretisation
+    if (hipMemsetAsync(h->flags, 0, 4 * sizeof(int), s) != hipSuccess) return fail(HELMHOLTZ_EHIP);
+    {
+        Level& v = h->lev[0];
+        const int64_t nv = int64_t(nz) * v.ncol;
+        hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(nv)), dim3(kBlock), 0, s, v.ncol, nz, kh,
+                           kv, delta, v.d.kh, v.d.kv, v.d.dl, h->flags);
+    }
+    for (int l = 1; l < h->L; ++l) {
+        Level& f = h->lev[l - 1];
+        Level& c = h->lev[l];
+        const int64_t nv = int64_t(nz) * c.ncol;
+        hipLaunchKernelGGL(k_coarsen, dim3(grid_for(nv)), dim3(kBlock), 0, s, f.ncol, c.ncol, nz,
+                           c.child, f.d.kh, f.d.kv, f.d.dl, c.d.kh, c.d.kv, c.d.dl);
+    }
+    for (int l = 0; l < h->L; ++l) {
+        Level& v = h->lev[l];
+        hipLaunchKernelGGL(k_factor, dim3((v.ncol + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
+                           view<double>(h, l), nz, v.d.cc, v.d.mm);
+        // float32 copies, rounded once from float64 (kh, kv, dl, cc, mm are
+        // contiguous in both precisions)
+        const int64_t nv = int64_t(nz) * v.ncol;
+        convert<double, float>(v.d.kh, v.f.kh, 2 * nv, s);
+        convert<double, float>(v.d.kv, v.f.kv, nv, s);
+        convert<double, float>(v.d.dl, v.f.dl, nv, s);
+        convert<double, float>(v.d.cc, v.f.cc, nv, s);
+        convert<double, float>(v.d.mm, v.f.mm, nv, s);
+    }
+    if (last_error() != HELMHOLTZ_OK) return fail(HELMHOLTZ_EHIP);
+    if (hipMemcpyAsync(h->hflags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
+        return fail(HELMHOLTZ_EHIP);
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(HELMHOLTZ_EHIP);
+    if (h->hflags[0] & 1) return fail(HELMHOLTZ_ENONFINITE);
+    if (h->hflags[0] & 2) return fail(HELMHOLTZ_EINVAL);
+    *out = h;
+    return HELMHOLTZ_OK;
+}
+
+int helmholtz_destroy(helmholtz_t h) {
+    if (!h) return HELMHOLTZ_EINVAL;
+    if (h->hsc) (void)hipHostFree(h->hsc);
+    delete h;
+    return HELMHOLTZ_OK;
+}
+
+int helmholtz_apply(helmholtz_t h, const double* x, double* y, int32_t batch,
+                    helmholtz_stream_t stream) {
+    if (int e = check_batch(h, batch)) return e;
+    if (!x || !y) return HELMHOLTZ_EINVAL;
+    launch_apply<double>(h, 0, x, y, batch, false, nullptr, reinterpret_cast<hipStream_t>(stream));
+    return last_error();
+}
+
+int helmholtz_vcycle(helmholtz_t h, const double* b, double* x, int32_t batch,
+                     helmholtz_stream_t stream) {
+    if (int e = check_batch(h, batch)) return e;
+    if (!b || !x) return HELMHOLTZ_EINVAL;
+    return precondition(h, b, x, batch, false, nullptr, reinterpret_cast<hipStream_t>(stream));
+}
+
+int helmholtz_vcycle_f32(helmholtz_t h, const float* b, float* x, int32_t batch,
+                         helmholtz_stream_t stream) {
+    if (int e = check_batch(h, batch)) return e;
+    if (!b || !x) return HELMHOLTZ_EINVAL;
+    vcycle_level<float>(h, 0, b, x, batch, nullptr, reinterpret_cast<hipStream_t>(stream));
+    return last_error();
+}
+
+int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, double rtol,
+                    int32_t maxiter, int32_t* iters, double* relres, helmholtz_stream_t stream) {
+    if (int e = check_batch(h, batch)) return e;
+    if (!b || !x || maxiter < 1 || !(rtol >= 0.0)) return HELMHOLTZ_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int64_t n = h->n;
+    const bool mixed = h->cfg.mg_precision == HELMHOLTZ_FP32;
+    const bool flex = h->cfg.cg_variant == HELMHOLTZ_CG_FLEXIBLE;
+    float* r32 = mixed ? h->lev[0].f.b : nullptr;
+    float* z32 = mixed ? h->lev[0].f.x : nullptr;
+    const dim3 red(kRedBlocks * batch), blk(kBlock);
+
+    for (int i = 0; i < batch; ++i) {
+        for (int j = 0; j < 8; ++j) h->hsc[i * 8 + j] = 0.0;
+        h->hsc[i * 8 + kRtol2] = rtol * rtol;
+    }
+    HH_CHECK(hipMemcpyAsync(h->sc, h->hsc, size_t(batch) * 8 * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+    // x = 0, r = b, ||b||^2
+    hipLaunchKernelGGL(k_cg_init, red, blk, 0, s, b, x, h->r, r32, n, kRedBlocks, h->partial,
+                       h->pstride);
+    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinBB), kRedBlocks, h->partial,
+                       nullptr, h->pstride, h->sc, h->active);
+    HH_CHECK(hipMemcpyAsync(h->hsc, h->sc, size_t(batch) * 8 * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    HH_CHECK(hipMemcpyAsync(h->hact, h->active, size_t(batch) * sizeof(int),
+                            hipMemcpyDeviceToHost, s));
+    HH_CHECK(hipStreamSynchronize(s));
+    if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
+    std::vector<double> bnorm2(batch);
+    std::vector<int32_t> it(batch, 0);
+    std::vector<double> rel(batch, 0.0);
+    bool any = false;
+    for (int i = 0; i < batch; ++i) {
+        bnorm2[i] = h->hsc[i * 8 + kBB];
+        if (!std::isfinite(bnorm2[i])) return HELMHOLTZ_ENONFINITE;
+        any = any || h->hact[i];
+        rel[i] = h->hact[i] ? 1.0 : 0.0;
+    }
+    auto finish = [&](int status) {
+        for (int i = 0; i < batch; ++i) {
+            if (iters) iters[i] = it[i];
+            if (relres) relres[i] = rel[i];
+        }
+        return status;
+    };
+    if (!any) return finish(HELMHOLTZ_OK);
+
+    // z = M r, rho = r.z, p = z
+    if (int e = precondition(h, h->r, mixed ? nullptr : h->z, batch, true, h->active, s)) return e;
+    if (mixed)
+        hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, nullptr, n, kRedBlocks,
+                           h->active, h->partial, nullptr, h->pstride);
+    else
+        hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, nullptr, n,
+                           kRedBlocks, h->active, h->partial, nullptr, h->pstride);
+    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinRho), kRedBlocks, h->partial,
+                       nullptr, h->pstride, h->sc, h->active);
+    if (mixed)
+        hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks, h->sc,
+                           h->active, 1);
+    else
+        hipLaunchKernelGGL((k_p_update<double>), red, blk, 0, s, h->z, h->p, n, kRedBlocks, h->sc,
+                           h->active, 1);
+
+    const int ntile0 = (h->lev[0].ncol + kBlock - 1) / kBlock;
+    const int nkc0 = (h->nz + kApplyChunk - 1) / kApplyChunk;
+    std::vector<int> was_active(batch);
+    int status = HELMHOLTZ_OK;
+    for (int iter = 1;; ++iter) {
+        for (int i = 0; i < batch; ++i) was_active[i] = h->hact[i];
+        // q = H p, alpha = rho / p.q
+        launch_apply<double>(h, 0, h->p, h->q, batch, true, h->active, s);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinAlpha), ntile0 * nkc0,
+                           h->partial, nullptr, h->pstride, h->sc, h->active);
+        // x += alpha p, r -= alpha q, ||r||^2, convergence flags
+        hipLaunchKernelGGL(k_cg_update, red, blk, 0, s, x, h->r, r32, h->p, h->q, n, kRedBlocks,
+                           h->sc, h->active, h->partial, h->pstride);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinRR), kRedBlocks,
+                           h->partial, nullptr, h->pstride, h->sc, h->active);
+        HH_CHECK(hipMemcpyAsync(h->hsc, h->sc, size_t(batch) * 8 * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        HH_CHECK(hipMemcpyAsync(h->hact, h->active, size_t(batch) * sizeof(int),
+                                hipMemcpyDeviceToHost, s));
+        HH_CHECK(hipStreamSynchronize(s));
+        if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
+        bool still = false;
+        for (int i = 0; i < batch; ++i) {
+            if (!was_active[i]) continue;
+            it[i] = iter;
+            const double rr = h->hsc[i * 8 + kRR];
+            if (!std::isfinite(rr)) return finish(HELMHOLTZ_ENONFINITE);
+            rel[i] = std::sqrt(rr / bnorm2[i]);
+            still = still || h->hact[i];
+        }
+        if (!still) break;
+        if (iter >= maxiter) {
+            status = HELMHOLTZ_NOT_CONVERGED;
+            break;
+        }
+        // z = M r, beta, p = z + beta p
+        if (int e = precondition(h, h->r, mixed ? nullptr : h->z, batch, true, h->active, s))
+            return e;
+        const double* qarg = flex ? h->q : nullptr;
+        if (mixed)
+            hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, qarg, n, kRedBlocks,
+                               h->active, h->partial, h->partial2, h->pstride);
+        else
+            hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, qarg, n,
+                               kRedBlocks, h->active, h->partial, h->partial2, h->pstride);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(flex ? kFinBetaFlex : kFinBeta),
+                           kRedBlocks, h->partial, h->partial2, h->pstride, h->sc, h->active);
+        if (mixed)
+            hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks,
+                               h->sc, h->active, 0);
+        else
+            hipLaunchKernelGGL((k_p_update<double>), red, blk, 0, s, h->z, h->p, n, kRedBlocks,
+                               h->sc, h->active, 0);
+    }
+    return finish(status);
+}
+
+int helmholtz_face_grad(helmholtz_t h, const double* lam, const double* x, int32_t batch,
+                        double* g_kh, double* g_kv, double* g_delta, helmholtz_stream_t stream) {
+    if (int e = check_batch(h, batch)) return e;
+    if (!lam || !x || !g_kh || !g_delta || (h->nz > 1 && !g_kv)) return HELMHOLTZ_EINVAL;
+    const Level& v = h->lev[0];
+    const int64_t total = int64_t(h->nz) * v.ncol;
+    const int grid = int((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_face_grad, dim3(grid), dim3(kBlock), 0,
+                       reinterpret_cast<hipStream_t>(stream), v.ncol, h->nz, v.nbr, lam, x, batch,
+                       g_kh, g_kv, g_delta);
+    return last_error();
+}
+
+}  // extern "C"

@@ -1,0 +1,604 @@
+// Device kernels of the Helmholtz multigrid path (gfx950, wave64).
+//
+// Data layout in HBM, per multigrid level with ncol columns and nz levels:
+//   vectors        [batch][nz][ncol]   column index fastest: lane = column gives
+//                                      one coalesced row per vertical level
+//   kh             [nz][2][ncol]       per level k: E faces, then N faces
+//   kv             [nz][ncol]          face k|k+1; row nz-1 is zero (no flux
+//                                      through the top), so loads need no guard
+//   dl (delta)     [nz][ncol]
+//   cc, mm         [nz][ncol]          factors of the column operator (below)
+//   nbr            [4][ncol]           E, W, N, S neighbour column
+//   fface          [2][ncol]           stored face index (slot*ncol + owner) of
+//                                      the W and S faces; E and N are c, ncol+c
+//
+// Column factorisation. The smoother solves with the column operator Hz (all
+// couplings inside a column plus the full diagonal of H; Section 3.5, Eq.
+// jacobi) by an LU factorisation computed once per operator (the paper
+// stores the same factors; Section 3.8). Pivots are computed in a form free
+// of cancellation: with s_k = delta_k + sum of the 4 horizontal couplings,
+// the top-down pivot excess is e_0 = s_0, e_k = s_k + kv_{k-1} e_{k-1} /
+// (e_{k-1} + kv_{k-1}), pivot p_k = e_k + kv_k. Stored: mm_k = 1/p_k and
+// cc_k = kv_k / p_k, so that forward elimination is t_k = r_k + cc_{k-1} t_{k-1}
+// and back substitution is z_k = mm_k t_k + cc_k z_{k+1}.
+// A "twisted" split at row `mid` factors rows below mid bottom-up instead
+// (f, q = f + kv_{k-1}, cc_k = kv_{k-1}/q_k) and row mid with both
+// neighbours eliminated; with mid = nz it is the plain top-down form.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hh {
+
+constexpr int kBlock = 256;
+
+// Workgroups of one launch are handed to the 8 XCDs round-robin (bid -> XCD
+// bid % 8). Renumber them so that each XCD works through one contiguous range
+// of logical blocks: neighbouring tiles (the N/S neighbour rows, the batch
+// members sharing coefficients) then meet in the same L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+    const int xcd = bid & 7, slot = bid >> 3;
+    const int q = nblocks >> 3, r = nblocks & 7;
+    return xcd * q + (xcd < r ? xcd : r) + slot;
+}
+
+template <typename T>
+struct LevelView {
+    int ncol, nz;
+    const int32_t* __restrict__ nbr;
+    const int32_t* __restrict__ fface;
+    const T* __restrict__ kh;
+    const T* __restrict__ kv;
+    const T* __restrict__ dl;
+    const T* __restrict__ cc;
+    const T* __restrict__ mm;
+};
+
+// ---------------------------------------------------------------------------
+// Block-Jacobi sweep (Eq. jacobi), one lane per column, whole column in
+// registers (NZMAX >= nz compile-time bound):
+//   x_new = x + omega Hz^-1 (b - H x)
+//         = (1 - omega) x + omega Hz^-1 (b + sum_d K_d x_nbr(d))
+// since H - Hz keeps only the horizontal off-diagonal couplings. The second
+// form needs no delta or kv, only the factors: 7 words per unknown instead of
+// 8. Neighbours read the old iterate (Jacobi); x and x_new must differ.
+// Modes: kZero x = 0 (first sweep of a level), kPlain, kProlong x += P xc
+// (first post-smoothing sweep, Algorithm 1 prolongation fused in),
+// kProlongZero x = P xc.
+enum SweepMode { kZero = 0, kPlain = 1, kProlong = 2, kProlongZero = 3 };
+
+template <typename T, int NZMAX, int MODE>
+__global__ void __launch_bounds__(kBlock)
+k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
+        const T* __restrict__ xc, const int32_t* __restrict__ parent, int ncol_c,
+        T* __restrict__ y, T omega, int batch, const int* __restrict__ active) {
+    constexpr bool kHasX = MODE == kPlain || MODE == kProlong;
+    constexpr bool kHasP = MODE == kProlong || MODE == kProlongZero;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int rhs = lb % batch, tile = lb / batch;
+    if (active && !active[rhs]) return;
+    const int ncol = L.ncol, nz = L.nz;
+    const int c = tile * kBlock + threadIdx.x;
+    if (c >= ncol) return;
+    const int64_t nv = int64_t(nz) * ncol;
+    b += rhs * nv;
+    y += rhs * nv;
+    if (kHasX) x += rhs * nv;
+    if (kHasP) xc += rhs * int64_t(nz) * ncol_c;
+
+    int nb[4] = {0, 0, 0, 0}, pn[5] = {0, 0, 0, 0, 0}, fW = 0, fS = 0;
+    if (MODE != kZero) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) nb[d] = L.nbr[d * ncol + c];
+        fW = L.fface[c];
+        fS = L.fface[ncol + c];
+        if (kHasP) {
+#pragma unroll
+            for (int d = 0; d < 4; ++d) pn[d] = parent[nb[d]];
+            pn[4] = parent[c];
+        }
+    }
+    auto xv = [&](int k, int col, int pcol) -> T {
+        T v = T(0);
+        if (kHasX) v = x[int64_t(k) * ncol + col];
+        if (kHasP) v += xc[int64_t(k) * ncol_c + pcol];
+        return v;
+    };
+
+    T u[NZMAX], cz[NZMAX], xo[NZMAX];
+    T tprev = T(0), cprev = T(0);
+#pragma unroll
+    for (int k = 0; k < NZMAX; ++k) {
+        if (k < nz) {
+            const int64_t row = int64_t(k) * ncol;
+            T r = b[row + c];
+            T xown = T(0);
+            if (MODE != kZero) {
+                const T* kh = L.kh + 2 * row;
+                const T xE = xv(k, nb[0], pn[0]), xW = xv(k, nb[1], pn[1]);
+                const T xN = xv(k, nb[2], pn[2]), xS = xv(k, nb[3], pn[3]);
+                xown = xv(k, c, pn[4]);
+                r += kh[c] * xE + kh[fW] * xW + kh[ncol + c] * xN + kh[fS] * xS;
+            }
+            const T ck = L.cc[row + c];
+            const T mk = L.mm[row + c];
+            const T t = r + cprev * tprev;
+            u[k] = mk * t;
+            cz[k] = ck;
+            xo[k] = xown;
+            tprev = t;
+            cprev = ck;
+        }
+    }
+    const T om = omega, om1 = T(1) - omega;
+    T z = T(0);
+#pragma unroll
+    for (int k = NZMAX - 1; k >= 0; --k) {
+        if (k < nz) {
+            z = u[k] + cz[k] * z;
+            y[int64_t(k) * ncol + c] = (MODE == kZero) ? om * z : om1 * xo[k] + om * z;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Operator apply y = H x in flux form (no cancellation of the large vertical
+// couplings against the diagonal). One thread per (column, chunk of levels);
+// keeps x[k-1], x[k], x[k+1] of its column in registers.
+// DOT additionally writes per-block partial sums of x . y (float64) for the
+// Krylov loop.
+template <typename T>
+__device__ __forceinline__ T flux_apply_row(const LevelView<T>& L, const T* __restrict__ x,
+                                            int k, int c, const int nb[4], int fW, int fS,
+                                            T xdn, T xo, T xup, T kvdn) {
+    const int ncol = L.ncol;
+    const int64_t row = int64_t(k) * ncol;
+    const T* kh = L.kh + 2 * row;
+    T y = L.dl[row + c] * xo;
+    y += kh[c] * (xo - x[row + nb[0]]);
+    y += kh[fW] * (xo - x[row + nb[1]]);
+    y += kh[ncol + c] * (xo - x[row + nb[2]]);
+    y += kh[fS] * (xo - x[row + nb[3]]);
+    y += L.kv[row + c] * (xo - xup);
+    y += kvdn * (xo - xdn);
+    return y;
+}
+
+// Sum over the block; the result is valid in thread 0. Fixed order, so
+// repeated runs give identical bits.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();  // earlier readers of sh are done
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < int(blockDim.x >> 6); ++i) s += sh[i];
+    }
+    return s;
+}
+
+template <typename T, bool DOT>
+__global__ void __launch_bounds__(kBlock)
+k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, int kchunk,
+        int nkc, double* __restrict__ partial, int pstride, const int* __restrict__ active) {
+    __shared__ double sh[kBlock / 64];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int rhs = lb % batch, rest = lb / batch;
+    const int kc = rest % nkc, tile = rest / nkc;
+    if (active && !active[rhs]) return;
+    const int ncol = L.ncol, nz = L.nz;
+    const int c = tile * kBlock + threadIdx.x;
+    const bool valid = c < ncol;
+    const int64_t nv = int64_t(nz) * ncol;
+    x += rhs * nv;
+    y += rhs * nv;
+    double acc = 0.0;
+    if (valid) {
+        int nb[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) nb[d] = L.nbr[d * ncol + c];
+        const int fW = L.fface[c], fS = L.fface[ncol + c];
+        const int k0 = kc * kchunk, k1 = min(nz, k0 + kchunk);
+        T xdn = k0 > 0 ? x[int64_t(k0 - 1) * ncol + c] : T(0);
+        T kvdn = k0 > 0 ? L.kv[int64_t(k0 - 1) * ncol + c] : T(0);
+        T xo = x[int64_t(k0) * ncol + c];
+        for (int k = k0; k < k1; ++k) {
+            const T xup = (k + 1 < nz) ? x[int64_t(k + 1) * ncol + c] : T(0);
+            const T v = flux_apply_row(L, x, k, c, nb, fW, fS, xdn, xo, xup, kvdn);
+            y[int64_t(k) * ncol + c] = v;
+            if (DOT) acc += double(xo) * double(v);
+            kvdn = L.kv[int64_t(k) * ncol + c];
+            xdn = xo;
+            xo = xup;
+        }
+    }
+    if (DOT) {
+        const double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + rest] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Residual and restriction fused (Algorithm 1): bc[k][C] = sum over the four
+// children ch of C of (b - H x)[k][ch], summed in the child order
+// (0,0),(1,0),(0,1),(1,1). The sum has no averaging factor: restriction is the
+// dual of injection (Section 3.6). ZEROX: x = 0, so bc = R b.
+template <typename T, bool ZEROX>
+__global__ void __launch_bounds__(kBlock)
+k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
+                 const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
+                 int batch, int kchunk, int nkc, const int* __restrict__ active) {
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int rhs = lb % batch, rest = lb / batch;
+    const int kc = rest % nkc, tile = rest / nkc;
+    if (active && !active[rhs]) return;
+    const int C = tile * kBlock + threadIdx.x;
+    if (C >= ncol_c) return;
+    const int ncol = F.ncol, nz = F.nz;
+    const int64_t nv = int64_t(nz) * ncol;
+    b += rhs * nv;
+    if (!ZEROX) x += rhs * nv;
+    bc += rhs * int64_t(nz) * ncol_c;
+    int ch[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ch[s] = child[s * ncol_c + C];
+    const int k0 = kc * kchunk, k1 = min(nz, k0 + kchunk);
+    if (ZEROX) {
+        for (int k = k0; k < k1; ++k) {
+            const int64_t row = int64_t(k) * ncol;
+            bc[int64_t(k) * ncol_c + C] =
+                ((b[row + ch[0]] + b[row + ch[1]]) + b[row + ch[2]]) + b[row + ch[3]];
+        }
+        return;
+    }
+    int nb[4][4], fW[4], fS[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) nb[s][d] = F.nbr[d * ncol + ch[s]];
+        fW[s] = F.fface[ch[s]];
+        fS[s] = F.fface[ncol + ch[s]];
+    }
+    for (int k = k0; k < k1; ++k) {
+        const int64_t row = int64_t(k) * ncol;
+        T r[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int cs = ch[s];
+            const T xo = x[row + cs];
+            const T xdn = k > 0 ? x[row - ncol + cs] : T(0);
+            const T xup = k + 1 < nz ? x[row + ncol + cs] : T(0);
+            const T kvdn = k > 0 ? F.kv[row - ncol + cs] : T(0);
+            r[s] = b[row + cs] - flux_apply_row(F, x, k, cs, nb[s], fW[s], fS[s], xdn, xo, xup, kvdn);
+        }
+        bc[int64_t(k) * ncol_c + C] = ((r[0] + r[1]) + r[2]) + r[3];
+    }
+}
+
+// Prolongation by natural injection on its own (only when there is no
+// post-smoothing sweep to fuse it into): y = x + xc[parent] (x may be null).
+template <typename T>
+__global__ void __launch_bounds__(kBlock)
+k_prolong(int ncol, int nz, int ncol_c, const int32_t* __restrict__ parent, const T* __restrict__ x,
+          const T* __restrict__ xc, T* __restrict__ y, int64_t total) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * kBlock) {
+        const int64_t per = int64_t(nz) * ncol;
+        const int64_t rhs = i / per, rem = i % per;
+        const int64_t k = rem / ncol;
+        const int c = int(rem % ncol);
+        const T v = xc[rhs * int64_t(nz) * ncol_c + k * ncol_c + parent[c]];
+        y[i] = x ? x[i] + v : v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Setup kernels (float64): coefficient layout, coarsening, factors, casts.
+
+// ABI layout -> internal layout on the finest level.
+__global__ void __launch_bounds__(kBlock)
+k_setup_fine(int ncol, int nz, const double* __restrict__ kh_in, const double* __restrict__ kv_in,
+             const double* __restrict__ dl_in, double* __restrict__ kh, double* __restrict__ kv,
+             double* __restrict__ dl, int* __restrict__ flags) {
+    const int64_t total = int64_t(nz) * ncol;
+    int bad = 0;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * kBlock) {
+        const int64_t k = i / ncol, c = i % ncol;
+        const double e = kh_in[i], n = kh_in[total + i];
+        const double v = (k + 1 < nz) ? kv_in[i] : 0.0;
+        const double d = dl_in[i];
+        kh[2 * k * ncol + c] = e;
+        kh[2 * k * ncol + ncol + c] = n;
+        kv[i] = v;
+        dl[i] = d;
+        if (!isfinite(e) || !isfinite(n) || !isfinite(v) || !isfinite(d)) bad |= 1;
+        if (!(e >= 0.0) || !(n >= 0.0) || !(v >= 0.0) || !(d > 0.0)) bad |= 2;
+    }
+    if (bad) atomicOr(flags, bad);
+}
+
+// Coarse coefficients by re-discretisation (Section 3.6 with the scalings of
+// Eq. DH_ratios): coarse E face = mean of the E faces of children (1,0),(1,1);
+// N face = mean of the N faces of (0,1),(1,1); kv and delta summed over all four.
+__global__ void __launch_bounds__(kBlock)
+k_coarsen(int ncol_f, int ncol_c, int nz, const int32_t* __restrict__ child,
+          const double* __restrict__ khf, const double* __restrict__ kvf,
+          const double* __restrict__ dlf, double* __restrict__ khc, double* __restrict__ kvc,
+          double* __restrict__ dlc) {
+    const int64_t total = int64_t(nz) * ncol_c;
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
+         i += int64_t(gridDim.x) * kBlock) {
+        const int64_t k = i / ncol_c;
+        const int C = int(i % ncol_c);
+        const int c00 = child[C], c10 = child[ncol_c + C], c01 = child[2 * ncol_c + C],
+                  c11 = child[3 * ncol_c + C];
+        const double* kf = khf + 2 * k * ncol_f;
+        khc[2 * k * ncol_c + C] = 0.5 * (kf[c10] + kf[c11]);
+        khc[2 * k * ncol_c + ncol_c + C] = 0.5 * (kf[ncol_f + c01] + kf[ncol_f + c11]);
+        const int64_t r = k * ncol_f;
+        kvc[i] = ((kvf[r + c00] + kvf[r + c10]) + kvf[r + c01]) + kvf[r + c11];
+        dlc[i] = ((dlf[r + c00] + dlf[r + c10]) + dlf[r + c01]) + dlf[r + c11];
+    }
+}
+
+// Column factors (see the header comment), one thread per column.
+__global__ void __launch_bounds__(kBlock)
+k_factor(LevelView<double> L, int mid, double* __restrict__ cc, double* __restrict__ mm) {
+    const int ncol = L.ncol, nz = L.nz;
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= ncol) return;
+    const int fW = L.fface[c], fS = L.fface[ncol + c];
+    auto s_of = [&](int k) {
+        const double* kh = L.kh + 2 * int64_t(k) * ncol;
+        return L.dl[int64_t(k) * ncol + c] + kh[c] + kh[fW] + kh[ncol + c] + kh[fS];
+    };
+    auto kv_of = [&](int k) { return L.kv[int64_t(k) * ncol + c]; };
+    const int top_end = mid < nz ? mid : nz;  // rows [0, top_end) top-down
+    double e = 0.0;
+    for (int k = 0; k < top_end; ++k) {
+        const double s = s_of(k);
+        if (k == 0) {
+            e = s;
+        } else {
+            const double a = kv_of(k - 1);
+            e = s + a * e / (e + a);
+        }
+        const double kvk = kv_of(k);
+        const double m = 1.0 / (e + kvk);
+        mm[int64_t(k) * ncol + c] = m;
+        cc[int64_t(k) * ncol + c] = kvk * m;
+    }
+    if (mid >= nz) return;
+    double f = 0.0;
+    for (int k = nz - 1; k > mid; --k) {
+        const double s = s_of(k);
+        if (k == nz - 1) {
+            f = s;
+        } else {
+            const double a = kv_of(k);
+            f = s + a * f / (f + a);
+        }
+        const double up = kv_of(k - 1);
+        const double m = 1.0 / (f + up);
+        mm[int64_t(k) * ncol + c] = m;
+        cc[int64_t(k) * ncol + c] = up * m;
+    }
+    double tau = s_of(mid);
+    if (mid > 0) {
+        const double a = kv_of(mid - 1);
+        tau += a * e / (e + a);
+    }
+    if (mid < nz - 1) {
+        const double a = kv_of(mid);
+        tau += a * f / (f + a);
+    }
+    mm[int64_t(mid) * ncol + c] = 1.0 / tau;
+    cc[int64_t(mid) * ncol + c] = 0.0;
+}
+
+template <typename S, typename D>
+__global__ void __launch_bounds__(kBlock)
+k_convert(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * kBlock)
+        dst[i] = D(src[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Krylov (float64) kernels. Reductions are deterministic: a fixed grid of
+// `nblk` blocks per right-hand side writes one partial each, and one block
+// per right-hand side adds the partials in a fixed order.
+//
+// Per right-hand-side scalars sc[rhs*8 + ...]:
+enum { kBB = 0, kRho = 1, kPQ = 2, kAlpha = 3, kRR = 4, kBeta = 5, kZQ = 6, kRtol2 = 7 };
+
+__device__ __forceinline__ void grid_range(int64_t n, int nblk, int blk, int64_t& i0, int64_t& i1) {
+    const int64_t per = (n + nblk - 1) / nblk;
+    i0 = min(n, int64_t(blk) * per);
+    i1 = min(n, i0 + per);
+}
+
+// x = 0, r = b, r32 = float(b); partial ||b||^2.
+__global__ void __launch_bounds__(kBlock)
+k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
+          float* __restrict__ r32, int64_t n, int nblk, double* __restrict__ partial, int pstride) {
+    __shared__ double sh[kBlock / 64];
+    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    int64_t i0, i1;
+    grid_range(n, nblk, blk, i0, i1);
+    const int64_t off = int64_t(rhs) * n;
+    double acc = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const double v = b[off + i];
+        x[off + i] = 0.0;
+        r[off + i] = v;
+        if (r32) r32[off + i] = float(v);
+        acc += v * v;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + blk] = s;
+}
+
+// x += alpha p; r -= alpha q; r32 = float(r); partial ||r||^2.
+__global__ void __launch_bounds__(kBlock)
+k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
+            const double* __restrict__ p, const double* __restrict__ q, int64_t n, int nblk,
+            const double* __restrict__ sc, const int* __restrict__ active,
+            double* __restrict__ partial, int pstride) {
+    __shared__ double sh[kBlock / 64];
+    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    if (!active[rhs]) return;
+    const double alpha = sc[rhs * 8 + kAlpha];
+    int64_t i0, i1;
+    grid_range(n, nblk, blk, i0, i1);
+    const int64_t off = int64_t(rhs) * n;
+    double acc = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        x[off + i] += alpha * p[off + i];
+        const double v = r[off + i] - alpha * q[off + i];
+        r[off + i] = v;
+        if (r32) r32[off + i] = float(v);
+        acc += v * v;
+    }
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + blk] = s;
+}
+
+// partial r . z (and z . q for the flexible beta).
+template <typename Z>
+__global__ void __launch_bounds__(kBlock)
+k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __restrict__ q,
+         int64_t n, int nblk, const int* __restrict__ active, double* __restrict__ partial,
+         double* __restrict__ partial2, int pstride) {
+    __shared__ double sh[kBlock / 64];
+    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    if (active && !active[rhs]) return;
+    int64_t i0, i1;
+    grid_range(n, nblk, blk, i0, i1);
+    const int64_t off = int64_t(rhs) * n;
+    double a1 = 0.0, a2 = 0.0;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const double zv = double(z[off + i]);
+        a1 += r[off + i] * zv;
+        if (q) a2 += zv * q[off + i];
+    }
+    const double s1 = block_sum(a1, sh);
+    if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + blk] = s1;
+    if (q) {
+        __syncthreads();
+        const double s2 = block_sum(a2, sh);
+        if (threadIdx.x == 0) partial2[int64_t(rhs) * pstride + blk] = s2;
+    }
+}
+
+// p = z + beta p (init: p = z).
+template <typename Z>
+__global__ void __launch_bounds__(kBlock)
+k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
+           const double* __restrict__ sc, const int* __restrict__ active, int init) {
+    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    if (!active[rhs]) return;
+    const double beta = init ? 0.0 : sc[rhs * 8 + kBeta];
+    int64_t i0, i1;
+    grid_range(n, nblk, blk, i0, i1);
+    const int64_t off = int64_t(rhs) * n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const double zv = double(z[off + i]);
+        p[off + i] = init ? zv : zv + beta * p[off + i];
+    }
+}
+
+// One block per right-hand side: add `cnt` partials in a fixed order.
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int cnt,
+                                                  double* sh) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) acc += part[i];
+    const double s = block_sum(acc, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) sh[0] = s;
+    __syncthreads();
+    return sh[0];
+}
+
+enum FinalizeMode { kFinBB = 0, kFinRho = 1, kFinAlpha = 2, kFinRR = 3, kFinBeta = 4, kFinBetaFlex = 5 };
+
+__global__ void __launch_bounds__(kBlock)
+k_finalize(int mode, int cnt, const double* __restrict__ partial,
+           const double* __restrict__ partial2, int pstride, double* __restrict__ sc,
+           int* __restrict__ active) {
+    __shared__ double sh[kBlock / 64];
+    const int rhs = blockIdx.x;
+    const bool act = active[rhs] != 0;
+    if (mode != kFinBB && !act) return;
+    const double s = reduce_partials(partial + int64_t(rhs) * pstride, cnt, sh);
+    double s2 = 0.0;
+    if (mode == kFinBetaFlex) s2 = reduce_partials(partial2 + int64_t(rhs) * pstride, cnt, sh);
+    if (threadIdx.x != 0) return;
+    double* v = sc + rhs * 8;
+    switch (mode) {
+        case kFinBB:
+            v[kBB] = s;
+            v[kRR] = s;
+            active[rhs] = (s > 0.0) ? 1 : 0;
+            break;
+        case kFinRho:
+            v[kRho] = s;
+            break;
+        case kFinAlpha:
+            v[kPQ] = s;
+            v[kAlpha] = v[kRho] / s;
+            break;
+        case kFinRR:
+            v[kRR] = s;
+            if (s <= v[kRtol2] * v[kBB]) active[rhs] = 0;
+            break;
+        case kFinBeta:
+            v[kBeta] = s / v[kRho];
+            v[kRho] = s;
+            break;
+        case kFinBetaFlex:
+            // Polak-Ribiere: z.(r_new - r_old) / rho with r_new - r_old = -alpha q
+            v[kBeta] = -v[kAlpha] * s2 / v[kRho];
+            v[kZQ] = s2;
+            v[kRho] = s;
+            break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Face-coefficient gradients of L = g . x (summed over the batch), written in
+// the ABI layout: g_kh[2][nz][ncol], g_kv[nz-1][ncol], g_delta[nz][ncol].
+__global__ void __launch_bounds__(kBlock)
+k_face_grad(int ncol, int nz, const int32_t* __restrict__ nbr, const double* __restrict__ lam,
+            const double* __restrict__ x, int batch, double* __restrict__ gkh,
+            double* __restrict__ gkv, double* __restrict__ gdl) {
+    const int64_t total = int64_t(nz) * ncol;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = int64_t(lb) * kBlock + threadIdx.x;
+    if (i >= total) return;
+    const int64_t k = i / ncol;
+    const int c = int(i % ncol);
+    const int e = nbr[c], nn = nbr[2 * ncol + c];
+    const int64_t row = k * ncol;
+    double ge = 0.0, gn = 0.0, gv = 0.0, gd = 0.0;
+    for (int bi = 0; bi < batch; ++bi) {
+        const double* l = lam + int64_t(bi) * total;
+        const double* xx = x + int64_t(bi) * total;
+        const double lc = l[row + c], xc = xx[row + c];
+        ge -= (lc - l[row + e]) * (xc - xx[row + e]);
+        gn -= (lc - l[row + nn]) * (xc - xx[row + nn]);
+        if (k + 1 < nz) gv -= (lc - l[row + ncol + c]) * (xc - xx[row + ncol + c]);
+        gd -= lc * xc;
+    }
+    gkh[i] = ge;
+    gkh[total + i] = gn;
+    if (k + 1 < nz) gkv[i] = gv;
+    gdl[i] = gd;
+}
+
+}  // namespace hh

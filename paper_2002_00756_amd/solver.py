@@ -1,0 +1,168 @@
+"""Python face of the HIP Helmholtz library: one operator hierarchy per object.
+
+``Operator`` owns a torch workspace on the device and a library handle.
+Its methods pass device pointers and the current HIP stream straight to the
+C ABI; nothing is computed in Python.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib
+
+
+def mesh_tables(N: int):
+    """Library-built mesh tables of C<N>: ``(nbr[4][6N^2], ftab[4][6N^2], parent[6N^2] or None)``."""
+    import numpy as np
+    lib = _lib.load()
+    ncol = 6 * N * N
+    nbr = np.empty((4, ncol), dtype=np.int32)
+    ftab = np.empty((4, ncol), dtype=np.int32)
+    par = np.empty(ncol, dtype=np.int32) if N % 2 == 0 else None
+    ptr = lambda a: a.ctypes.data_as(_lib._i32p) if a is not None else None
+    _lib.check(lib.helmholtz_mesh_tables(N, ptr(nbr), ptr(ftab), ptr(par)), "mesh_tables")
+    return nbr, ftab, par
+
+
+def _stream_ptr(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, device, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(t)
+    t = t.to(device=device, dtype=dtype).contiguous()
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+@dataclasses.dataclass
+class SolveResult:
+    x: torch.Tensor
+    iters: list
+    relres: list
+    converged: bool
+
+
+class Operator:
+    """Helmholtz operator hierarchy on one GPU.
+
+    Parameters follow P_H^(MG)(L, omega, n_pre, n_post) with n_coarse sweeps on
+    the coarsest level. ``precision`` is the V-cycle arithmetic ("fp64" or
+    "fp32"); the Krylov loop is always float64. ``cg`` selects the beta of the
+    conjugate-gradient update ("standard" or "flexible").
+    """
+
+    def __init__(self, N, nz, kh, kv, delta, nlevels, n_pre=2, n_post=2, n_coarse=4,
+                 omega=0.8, precision="fp64", cg="standard", max_batch=1, device="cuda"):
+        self.lib = _lib.load()
+        self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.N, self.nz, self.nlevels = int(N), int(nz), int(nlevels)
+        self.ncol = 6 * self.N * self.N
+        self.precision = precision
+        self.cfg = _lib.Config(self.N, self.nz, self.nlevels, n_pre, n_post, n_coarse,
+                               float(omega), _lib.FP32 if precision == "fp32" else _lib.FP64,
+                               _lib.CG_FLEXIBLE if cg == "flexible" else _lib.CG_STANDARD,
+                               int(max_batch))
+        self.max_batch = int(max_batch)
+        nbytes = self.lib.helmholtz_workspace_bytes(ctypes.byref(self.cfg))
+        if nbytes == 0:
+            raise _lib.HelmholtzError(_lib.EINVAL if self.N % (1 << (self.nlevels - 1)) == 0
+                                      else _lib.ESHAPE, "workspace_bytes")
+        self.workspace_bytes = nbytes
+        raw = torch.empty(nbytes + _lib.WORKSPACE_ALIGN, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % _lib.WORKSPACE_ALIGN
+        self._raw = raw
+        self._ws_ptr = raw.data_ptr() + off
+        kh = _dev(kh, torch.float64, self.device, (2, self.nz, self.ncol))
+        delta = _dev(delta, torch.float64, self.device, (self.nz, self.ncol))
+        kv = _dev(kv, torch.float64, self.device, (self.nz - 1, self.ncol)) if self.nz > 1 else None
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            code = self.lib.helmholtz_create(
+                ctypes.byref(self.cfg), kh.data_ptr(), kv.data_ptr() if kv is not None else None,
+                delta.data_ptr(), self._ws_ptr, nbytes, _stream_ptr(self.device),
+                ctypes.byref(handle))
+        _lib.check(code, "helmholtz_create")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.lib.helmholtz_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers -----------------------------------------------------------
+    def _vec(self, v, dtype=torch.float64):
+        v = _dev(v, dtype, self.device)
+        squeeze = v.dim() == 2
+        if squeeze:
+            v = v.unsqueeze(0)
+        if v.dim() != 3 or tuple(v.shape[1:]) != (self.nz, self.ncol):
+            raise ValueError(f"vector must be [batch][{self.nz}][{self.ncol}], got {tuple(v.shape)}")
+        if v.shape[0] > self.max_batch:
+            raise ValueError(f"batch {v.shape[0]} exceeds max_batch {self.max_batch}")
+        return v, squeeze
+
+    # -- operations --------------------------------------------------------
+    def apply(self, x):
+        """y = H x (float64)."""
+        x, sq = self._vec(x)
+        y = torch.empty_like(x)
+        _lib.check(self.lib.helmholtz_apply(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                            _stream_ptr(self.device)), "helmholtz_apply")
+        return y[0] if sq else y
+
+    def vcycle(self, b):
+        """x = M b, one V-cycle from zero in the operator's precision (float64 in and out)."""
+        b, sq = self._vec(b)
+        x = torch.empty_like(b)
+        _lib.check(self.lib.helmholtz_vcycle(self._h, b.data_ptr(), x.data_ptr(), b.shape[0],
+                                             _stream_ptr(self.device)), "helmholtz_vcycle")
+        return x[0] if sq else x
+
+    def vcycle_f32(self, b):
+        """x = M b entirely in float32."""
+        b, sq = self._vec(b, torch.float32)
+        x = torch.empty_like(b)
+        _lib.check(self.lib.helmholtz_vcycle_f32(self._h, b.data_ptr(), x.data_ptr(), b.shape[0],
+                                                 _stream_ptr(self.device)),
+                   "helmholtz_vcycle_f32")
+        return x[0] if sq else x
+
+    def solve(self, b, rtol=1e-8, maxiter=200, out=None) -> SolveResult:
+        """MG-preconditioned CG from x = 0; returns the solution and per-RHS statistics."""
+        b, sq = self._vec(b)
+        x = torch.empty_like(b) if out is None else out.view(b.shape)
+        nb = b.shape[0]
+        iters = (ctypes.c_int32 * nb)()
+        rel = (ctypes.c_double * nb)()
+        code = self.lib.helmholtz_solve(self._h, b.data_ptr(), x.data_ptr(), nb, float(rtol),
+                                        int(maxiter), iters, rel, _stream_ptr(self.device))
+        _lib.check(code, "helmholtz_solve", allow_not_converged=True)
+        return SolveResult(x[0] if sq else x, list(iters), list(rel), code == _lib.OK)
+
+    def face_grad(self, lam, x):
+        """Coefficient gradients of L = g . x given lam = H^-1 g, summed over the batch."""
+        lam, _ = self._vec(lam)
+        x, _ = self._vec(x)
+        gkh = torch.empty((2, self.nz, self.ncol), dtype=torch.float64, device=self.device)
+        gkv = torch.empty((max(self.nz - 1, 0), self.ncol), dtype=torch.float64,
+                          device=self.device)
+        gdl = torch.empty((self.nz, self.ncol), dtype=torch.float64, device=self.device)
+        _lib.check(self.lib.helmholtz_face_grad(
+            self._h, lam.data_ptr(), x.data_ptr(), lam.shape[0], gkh.data_ptr(),
+            gkv.data_ptr() if self.nz > 1 else None, gdl.data_ptr(), _stream_ptr(self.device)),
+            "helmholtz_face_grad")
+        return gkh, gkv, gdl

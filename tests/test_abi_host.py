@@ -1,0 +1,101 @@
+"""Host-only checks of the C ABI: the library loads, exports what the header
+declares, sizes its workspace, rejects bad input before touching the GPU, and
+builds mesh tables bit-identical to the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import mesh as omesh
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2002_00756_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2002_00756_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "helmholtz.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(helmholtz_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2002_00756_amd import _lib
+    names = _declared_functions()
+    assert len(names) == 10
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in _lib.SIGNATURES, n
+
+
+def _cfg(N=12, nz=10, L=3, **kw):
+    from paper_2002_00756_amd import _lib
+    d = dict(n_pre=2, n_post=2, n_coarse=4, omega=0.8, mg_precision=0, cg_variant=0, max_batch=1)
+    d.update(kw)
+    return _lib.Config(N, nz, L, d["n_pre"], d["n_post"], d["n_coarse"], d["omega"],
+                       d["mg_precision"], d["cg_variant"], d["max_batch"])
+
+
+def test_workspace_bytes(lib):
+    small = lib.helmholtz_workspace_bytes(ctypes.byref(_cfg()))
+    big = lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(max_batch=4)))
+    assert 0 < small < big
+    # C192 x 70 with 6 levels: per level 6 float64 + 6 float32 coefficient words, ...
+    c192 = lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(192, 70, 6)))
+    n = 6 * 192 * 192 * 70
+    assert 72 * n < c192 < 200 * n
+    for bad in (_cfg(12, 10, 4),            # 12 not divisible by 8
+                _cfg(12, 0, 1), _cfg(12, 129, 1), _cfg(12, 10, 3, n_coarse=0),
+                _cfg(12, 10, 3, omega=0.0), _cfg(12, 10, 3, max_batch=0),
+                _cfg(12, 10, 3, mg_precision=2)):
+        assert lib.helmholtz_workspace_bytes(ctypes.byref(bad)) == 0
+
+
+def test_create_rejects_before_touching_the_device(lib):
+    from paper_2002_00756_amd import _lib
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(256)
+    assert lib.helmholtz_create(ctypes.byref(_cfg(12, 10, 4)), dummy, dummy, dummy, dummy,
+                                1 << 30, None, ctypes.byref(h)) == _lib.ESHAPE
+    assert lib.helmholtz_create(ctypes.byref(_cfg(omega=2.0)), dummy, dummy, dummy, dummy,
+                                1 << 30, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.helmholtz_create(ctypes.byref(_cfg()), dummy, dummy, dummy, None,
+                                1 << 30, None, ctypes.byref(h)) == _lib.EWORKSPACE
+    assert lib.helmholtz_create(ctypes.byref(_cfg()), dummy, dummy, dummy, ctypes.c_void_p(4096),
+                                16, None, ctypes.byref(h)) == _lib.EWORKSPACE
+    assert lib.helmholtz_create(ctypes.byref(_cfg()), dummy, dummy, dummy,
+                                ctypes.c_void_p(4096 + 8), 1 << 40, None,
+                                ctypes.byref(h)) == _lib.EWORKSPACE
+    assert lib.helmholtz_create(ctypes.byref(_cfg()), None, dummy, dummy, dummy,
+                                1 << 30, None, ctypes.byref(h)) == _lib.EINVAL
+    assert not h.value
+    for fn in ("helmholtz_apply", "helmholtz_vcycle", "helmholtz_vcycle_f32"):
+        assert getattr(lib, fn)(None, dummy, dummy, 1, None) == _lib.EINVAL
+    assert lib.helmholtz_destroy(None) == _lib.EINVAL
+
+
+def test_strerror(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5, 99):
+        assert isinstance(lib.helmholtz_strerror(code), bytes)
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 6, 12, 48, 96, 192, 384])
+def test_mesh_tables_bit_exact(lib, N):
+    from paper_2002_00756_amd.solver import mesh_tables
+    nbr, ftab, par = mesh_tables(N)
+    ref_nbr = omesh.neighbours(N)
+    assert np.array_equal(nbr, ref_nbr)
+    assert np.array_equal(ftab, omesh.face_table(N, ref_nbr))
+    if N % 2 == 0:
+        assert np.array_equal(par, omesh.parent(N))
+    else:
+        assert par is None
