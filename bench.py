@@ -1,0 +1,315 @@
+#!/usr/bin/env python
+"""Helmholtz multigrid benchmark on one MI355X.
+
+Workload: cubed-sphere C192 x 70 (221,184 columns, 15,482,880 unknowns),
+synthetic SPD face-coupling operator (w_h = 1, w_v = 1000 graded with
+exp(-k/20), delta ~ U[0.5, 1.5]), b ~ N(0, 1), 6-level V-cycle (2/2 block-Jacobi
+sweeps, omega = 0.8, 4 coarse sweeps).
+
+A step is one complete solve of H x = b to relative residual 1e-6 by
+conjugate gradients in float64 preconditioned by one float32 V-cycle per
+iteration (operator apply, smoothing with column tridiagonal solves,
+residual + restriction, prolongation, coarse sweeps, float64 Krylov
+updates), with b and x resident in HBM. `value` is solves per second.
+The float64-only solve on the same seed, the V-cycle alone, the set-up, the
+adjoint (backward) step and the oracle on the host CPU are reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+
+
+def vcycle_words(L, n_pre, n_post, n_coarse):
+    """Algorithmic words per finest-level unknown of one V-cycle with these kernels.
+
+    Per level: first sweep from zero 4 words (b, two column factors, x_new),
+    further sweeps 7 (b, x, two face couplings, two factors, x_new), fused
+    residual + restriction 6 + 1/4 (b, x, kh[2], kv, delta; coarse b), sweep
+    with fused prolongation 7 + 1/4 (coarse x). Level l has 4^-l of the
+    finest level's unknowns.
+    """
+    def smooth(n, first_zero):
+        if n == 0:
+            return 0.0
+        return (4.0 if first_zero else 7.0) + 7.0 * (n - 1)
+
+    total = 0.0
+    for l in range(L - 1):
+        words = smooth(n_pre, True)
+        words += 6.25 if n_pre > 0 else 1.25
+        if n_post > 0:
+            words += 7.25 + 7.0 * (n_post - 1)
+        else:
+            words += 2.25
+        total += words * 4.0 ** (-l)
+    total += smooth(n_coarse, True) * 4.0 ** (-(L - 1))
+    return total
+
+
+def cg_bytes_per_unknown(vc_words, mixed, flexible):
+    """Algorithmic bytes per unknown of one CG iteration (outer loop in float64)."""
+    apply_dot = 6 * 8                      # p, kh[2], kv, delta read; q written
+    update = 4 * 8 + 2 * 8 + (4 if mixed else 0)   # x, p, r, q read; x, r (, r32) written
+    vc = vc_words * (4 if mixed else 8)
+    zsz = 4 if mixed else 8
+    dot = 8 + zsz + (8 if flexible else 0)
+    pupd = zsz + 8 + 8
+    return apply_dot + update + vc + dot + pupd
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(w, kh, kv, delta, b, iters):
+    """Time the float64 oracle on one host core on a bounded sample.
+
+    Sample: one operator apply plus one V-cycle at the full C192 x 70 size,
+    the dominant work of one preconditioned CG iteration; solves/s is
+    extrapolated with the iteration count the float64 solve needs.
+    """
+    from oracle import helmholtz, mesh, multigrid
+    t0 = time.perf_counter()
+    levels, parents, childs = mesh.hierarchy(w.N, w.nlevels)
+    hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta)
+    t1 = time.perf_counter()
+    y = hier.apply(0, b)
+    t2 = time.perf_counter()
+    z = multigrid.vcycle(hier, b)
+    t3 = time.perf_counter()
+    del y, z
+    t_iter = (t2 - t1) + (t3 - t2)
+    return {
+        "value": 1.0 / (iters * t_iter),
+        "unit": "solves/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one float64 apply ({t2 - t1:.2f} s) + one V-cycle ({t3 - t2:.2f} s) of the "
+                   f"NumPy oracle at {w.name} on 1 host core ({cpu_model()}), scaled to "
+                   f"{iters} CG iterations per solve; oracle set-up {t1 - t0:.2f} s not counted"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="C192x70", choices=sorted(workloads.ALL))
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cg", default="standard", choices=["standard", "flexible"])
+    ap.add_argument("--probe", action="store_true",
+                    help="for counter runs: a few solves plus a 1 GiB device copy of known "
+                         "size, no JSON")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2002_00756_amd import Operator, _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2002_00756_amd import build
+        build.build()
+
+    w = workloads.ALL[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    kh, kv, delta = workloads.workload_coefficients(w)
+    b_np = workloads.rhs(w.N, w.nz)[0]
+    prm = dict(n_pre=2, n_post=2, n_coarse=4, omega=0.8)
+
+    # --- set-up (mesh tables, coarse operators, factors, float32 copies) ---
+    kh_d = torch.from_numpy(kh).to(dev)
+    kv_d = torch.from_numpy(kv).to(dev)
+    dl_d = torch.from_numpy(delta).to(dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op32 = Operator(w.N, w.nz, kh_d, kv_d, dl_d, w.nlevels, precision="fp32", cg=args.cg,
+                    device=dev, **prm)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    op64 = Operator(w.N, w.nz, kh_d, kv_d, dl_d, w.nlevels, precision="fp64", cg="standard",
+                    device=dev, **prm)
+    b = torch.from_numpy(b_np).to(dev)
+    x = torch.empty_like(b)
+    stream = torch.cuda.current_stream(dev)
+
+    def timed_solves(op, steps, warmup):
+        for _ in range(warmup):
+            op.solve(b, rtol=args.rtol, out=x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        its = []
+        e0.record(stream)
+        t = time.perf_counter()
+        for _ in range(steps):
+            res = op.solve(b, rtol=args.rtol, out=x)
+            its.append(res.iters[0])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        return e0.elapsed_time(e1) / steps, wall / steps * 1e3, its, res
+
+    if args.probe:
+        for _ in range(max(args.steps, 1)):
+            op32.solve(b, rtol=args.rtol, out=x)
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)          # reads and writes exactly 1 GiB each
+        torch.cuda.synchronize()
+        print("probe done", flush=True)
+        return
+
+    # --- the metric: mixed-precision solves -------------------------------
+    op32.profile(True)
+    ms32, wall32, its32, res32 = timed_solves(op32, args.steps, args.warmup)
+    sweep_ms, sweep_n, sweep_bytes = op32.profile_read(_lib.PROF_SWEEP_FINE)
+    op32.profile(False)
+    x32 = x.clone()
+    true32 = float(torch.linalg.norm(b - op64.apply(x32)) / torch.linalg.norm(b))
+
+    # --- float64-only path on the same seed ---------------------------------
+    op64.profile(True)
+    ms64, wall64, its64, res64 = timed_solves(op64, args.steps, args.warmup)
+    sw64_ms, sw64_n, sw64_bytes = op64.profile_read(_lib.PROF_SWEEP_FINE)
+    ap_ms, ap_n, ap_bytes = op64.profile_read(_lib.PROF_APPLY_FINE)
+    op64.profile(False)
+    x64 = x.clone()
+    true64 = float(torch.linalg.norm(b - op64.apply(x64)) / torch.linalg.norm(b))
+    # reference solution: float64 solve to 1e-12
+    xref = op64.solve(b, rtol=1e-12).x
+    err32 = float(torch.linalg.norm(x32 - xref) / torch.linalg.norm(xref))
+    err64 = float(torch.linalg.norm(x64 - xref) / torch.linalg.norm(xref))
+
+    # --- V-cycle alone --------------------------------------------------------
+    words = vcycle_words(w.nlevels, prm["n_pre"], prm["n_post"], prm["n_coarse"])
+    n = w.n
+
+    def time_vcycle(fn, arg, reps=20):
+        for _ in range(3):
+            fn(arg)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn(arg)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    b32 = b.float()
+    vc32_ms = time_vcycle(op32.vcycle_f32, b32)
+    vc64_ms = time_vcycle(op64.vcycle, b)
+    vc32_gbs = words * 4 * n / (vc32_ms * 1e-3) / 1e9
+    vc64_gbs = words * 8 * n / (vc64_ms * 1e-3) / 1e9
+
+    # --- adjoint step: forward solve + adjoint solve + face gradients ---------
+    g = torch.from_numpy(workloads.loss_weights(w.N, w.nz)[0]).to(dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps_adj = max(1, min(3, args.steps))
+    for _ in range(reps_adj):
+        xf = op32.solve(b, rtol=args.rtol).x
+        lam = op32.solve(g, rtol=args.rtol).x
+        op32.face_grad(lam, xf)
+    torch.cuda.synchronize()
+    adj_ms = (time.perf_counter() - t) / reps_adj * 1e3
+
+    # --- dominant kernel: fine-level float32 smoothing sweep -----------------
+    sweep_avg_ms = sweep_ms / max(sweep_n, 1)
+    achieved = (sweep_bytes / max(sweep_n, 1)) / (sweep_avg_ms * 1e-3) / 1e9
+    traffic = None
+    tfile = os.path.join(ROOT, "profiles", "traffic_sweep_f32_C192x70.json")
+    if os.path.exists(tfile):
+        traffic = json.load(open(tfile)).get("bytes_per_launch")
+
+    per_iter32 = cg_bytes_per_unknown(words, True, args.cg == "flexible")
+    per_iter64 = cg_bytes_per_unknown(words, False, False)
+    it32 = float(np.mean(its32))
+    it64 = float(np.mean(its64))
+    out = {
+        "metric": "Helmholtz solves/s (FP32-MG preconditioned FP64 CG to rel res 1e-6)",
+        "value": 1e3 / ms32,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 V-cycle + f64 CG",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name} cubed sphere ({w.ncol} columns x {w.nz} levels, "
+                        f"{w.n} unknowns), w_h={w.w_h}, w_v={w.w_v}"
+                        f"{' graded exp(-k/20)' if w.graded else ''}",
+            "levels": w.nlevels, "n_pre": 2, "n_post": 2, "n_coarse": 4, "omega": 0.8,
+            "rtol": args.rtol, "cg": args.cg, "batch": 1,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_sweep<float> plain mode, finest level",
+            "achieved": achieved,
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": achieved / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "avg_launch_us": sweep_avg_ms * 1e3,
+            "launches": sweep_n,
+            "algorithmic_bytes_per_launch": sweep_bytes / max(sweep_n, 1),
+        },
+        "fp32_mg": {
+            "solves_per_s": 1e3 / ms32, "ms_per_solve": ms32, "host_wall_ms": wall32,
+            "iters": it32, "true_relres": true32, "err_vs_fp64_1e-12": err32,
+            "cg_GBps": it32 * per_iter32 * n / (ms32 * 1e-3) / 1e9,
+        },
+        "fp64_mg": {
+            "solves_per_s": 1e3 / ms64, "ms_per_solve": ms64, "host_wall_ms": wall64,
+            "iters": it64, "true_relres": true64, "err_vs_fp64_1e-12": err64,
+            "cg_GBps": it64 * per_iter64 * n / (ms64 * 1e-3) / 1e9,
+            "sweep_fine_GBps": (sw64_bytes / max(sw64_n, 1)) / (sw64_ms / max(sw64_n, 1) * 1e-3)
+            / 1e9 if sw64_n else None,
+            "apply_fine_GBps": (ap_bytes / max(ap_n, 1)) / (ap_ms / max(ap_n, 1) * 1e-3) / 1e9
+            if ap_n else None,
+        },
+        "speedup_fp32mg_vs_fp64": ms64 / ms32,
+        "vcycle": {
+            "words_per_unknown": words,
+            "fp32_ms": vc32_ms, "fp32_GBps": vc32_gbs, "fp32_frac": vc32_gbs / PEAK_HBM_GBS,
+            "fp64_ms": vc64_ms, "fp64_GBps": vc64_gbs, "fp64_frac": vc64_gbs / PEAK_HBM_GBS,
+        },
+        "setup_ms": setup_ms,
+        "adjoint_step_ms": adj_ms,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, kh, kv, delta, b_np, int(round(it64)))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -71,7 +71,7 @@ enum {
 enum { HELMHOLTZ_FP64 = 0, HELMHOLTZ_FP32 = 1 };               /* V-cycle precision   */
 enum { HELMHOLTZ_CG_STANDARD = 0, HELMHOLTZ_CG_FLEXIBLE = 1 };  /* beta of the CG loop */
 
-#define HELMHOLTZ_NZ_MAX 128
+#define HELMHOLTZ_NZ_MAX 120
 #define HELMHOLTZ_WORKSPACE_ALIGN 256
 
 typedef struct {
@@ -157,6 +157,24 @@ int helmholtz_face_grad(helmholtz_t h, const double* lam, const double* x, int32
  *   parent [6N^2]     column of C<N/2> that contains each column (NULL, or ignored if N is odd)
  * Pure host function. */
 int helmholtz_mesh_tables(int32_t N, int32_t* nbr, int32_t* ftab, int32_t* parent);
+
+/* Kernel timing (instrumentation, not part of the method). While enabled,
+ * every launch of the profiled kernels is bracketed by HIP events on the
+ * stream it runs on; helmholtz_profile_read waits for the recorded events
+ * and returns the accumulated device time, the number of launches and the
+ * algorithmic bytes those launches had to move (the words each unknown must
+ * read and write, times the unknowns processed). Enabling resets the counts.
+ * Profiled kernels:
+ *   HELMHOLTZ_PROF_SWEEP_FINE   block-Jacobi sweep on the finest level
+ *                               (plain mode: reads b, x, two face couplings
+ *                               and the two column factors, writes x_new:
+ *                               7 words per unknown)
+ *   HELMHOLTZ_PROF_APPLY_FINE   float64 operator apply on the finest level
+ *                               (reads x, kh[2], kv, delta, writes y: 6 words) */
+enum { HELMHOLTZ_PROF_SWEEP_FINE = 0, HELMHOLTZ_PROF_APPLY_FINE = 1, HELMHOLTZ_PROF_COUNT = 2 };
+int helmholtz_profile_enable(helmholtz_t h, int enable);
+int helmholtz_profile_read(helmholtz_t h, int32_t kernel, double* ms /* host */,
+                           int64_t* launches /* host */, double* bytes /* host */);
 
 /* Static description of a return code. */
 const char* helmholtz_strerror(int code);

@@ -16,7 +16,7 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, ESHAPE, EWORKSPACE, ENONFINITE, EHIP = -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 CG_STANDARD, CG_FLEXIBLE = 0, 1
-NZ_MAX = 128
+NZ_MAX = 120
 WORKSPACE_ALIGN = 256
 
 # Every function the header declares, with (restype, argtypes).
@@ -46,7 +46,11 @@ SIGNATURES = {
     "helmholtz_face_grad": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _dp, _dp, _dp, _vp]),
     "helmholtz_mesh_tables": (_c_int, [ctypes.c_int32, _i32p, _i32p, _i32p]),
     "helmholtz_strerror": (ctypes.c_char_p, [_c_int]),
+    "helmholtz_profile_enable": (_c_int, [_vp, _c_int]),
+    "helmholtz_profile_read": (_c_int, [_vp, ctypes.c_int32, _f64p,
+                                        ctypes.POINTER(ctypes.c_int64), _f64p]),
 }
+PROF_SWEEP_FINE, PROF_APPLY_FINE = 0, 1
 
 _lib = None
 

@@ -11,7 +11,7 @@
 #include <type_traits>
 #include <vector>
 
-#include "../../include/helmholtz.h"
+#include "helmholtz.h"
 #include "kernels.hpp"
 #include "mesh.hpp"
 
@@ -19,8 +19,8 @@ using namespace hh;
 
 namespace {
 
-constexpr int kRedBlocks = 512;  // partial sums per right-hand side for vector reductions
-constexpr int kApplyChunk = 8;   // vertical levels per thread in apply / residual kernels
+constexpr int kRedBlocks = 2048;  // partial sums per right-hand side for vector reductions
+constexpr int kApplyChunk = 4;   // vertical levels per thread in apply / residual kernels
 
 template <typename T>
 struct LevelData {
@@ -104,6 +104,15 @@ struct helmholtz_s {
     int* hact = nullptr;
     int* hflags = nullptr;
     size_t ws_bytes = 0;
+    // kernel timing hook: event pairs recorded around profiled launches
+    struct Prof {
+        double ms = 0.0, bytes = 0.0;
+        int64_t launches = 0;
+        std::vector<hipEvent_t> start, stop;
+        std::vector<double> pend_bytes;
+    };
+    bool prof_on = false;
+    mutable Prof prof[HELMHOLTZ_PROF_COUNT];
 };
 
 namespace {
@@ -177,6 +186,49 @@ inline int grid_for(int64_t n) {
 
 inline int last_error() { return hipGetLastError() == hipSuccess ? HELMHOLTZ_OK : HELMHOLTZ_EHIP; }
 
+// Fold the finished event pairs of one profiled kernel into its totals.
+int prof_flush(const helmholtz_s* h, int kernel) {
+    helmholtz_s::Prof& P = h->prof[kernel];
+    for (size_t i = 0; i < P.start.size(); ++i) {
+        float ms = 0.f;
+        if (hipEventSynchronize(P.stop[i]) != hipSuccess) return HELMHOLTZ_EHIP;
+        if (hipEventElapsedTime(&ms, P.start[i], P.stop[i]) != hipSuccess) return HELMHOLTZ_EHIP;
+        P.ms += ms;
+        P.bytes += P.pend_bytes[i];
+        P.launches += 1;
+        (void)hipEventDestroy(P.start[i]);
+        (void)hipEventDestroy(P.stop[i]);
+    }
+    P.start.clear();
+    P.stop.clear();
+    P.pend_bytes.clear();
+    return HELMHOLTZ_OK;
+}
+
+// Record an event before a profiled launch; returns false when profiling is off.
+bool prof_begin(const helmholtz_s* h, int kernel, hipStream_t s) {
+    if (!h->prof_on) return false;
+    helmholtz_s::Prof& P = h->prof[kernel];
+    if (P.start.size() >= 256 && prof_flush(h, kernel) != HELMHOLTZ_OK) return false;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return false;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return false;
+    }
+    P.start.push_back(a);
+    P.stop.push_back(b);
+    P.pend_bytes.push_back(0.0);
+    (void)hipEventRecord(a, s);
+    return true;
+}
+
+void prof_end(const helmholtz_s* h, int kernel, double bytes, hipStream_t s) {
+    helmholtz_s::Prof& P = h->prof[kernel];
+    P.pend_bytes.back() = bytes;
+    (void)hipEventRecord(P.stop.back(), s);
+}
+
 template <typename T>
 LevelView<T> view(const helmholtz_s* h, int l) {
     const Level& v = h->lev[l];
@@ -193,34 +245,39 @@ LevelData<T>& data(helmholtz_s* h, int l) {
     else return h->lev[l].f;
 }
 
-// ---- sweep launch: compile-time column length bucket --------------------
-template <typename T, int NZMAX, int MODE>
+// ---- sweep launch: compile-time bound on levels per thread ---------------
+inline int sweep_mid(int nz) { return nz / 2; }
+
+template <typename T, int JMAX, int MODE>
 void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
                     int batch, const int* active, hipStream_t s) {
     const Level& v = h->lev[l];
-    const int ntile = (v.ncol + kBlock - 1) / kBlock;
+    constexpr int TC = SweepTile<T>::TC;
+    const int ntile = (v.ncol + TC - 1) / TC;
     const int32_t* par = (l + 1 < h->L) ? v.parent : nullptr;
     const int ncol_c = (l + 1 < h->L) ? h->lev[l + 1].ncol : 0;
-    hipLaunchKernelGGL((k_sweep<T, NZMAX, MODE>), dim3(ntile * batch), dim3(kBlock), 0, s,
-                       view<T>(h, l), b, x, xc, par, ncol_c, y, T(h->cfg.omega), batch, active);
+    const bool prof = (l == 0 && MODE == kPlain) && prof_begin(h, HELMHOLTZ_PROF_SWEEP_FINE, s);
+    hipLaunchKernelGGL((k_sweep<T, JMAX, MODE>), dim3(ntile * batch), dim3(kBlock),
+                       SweepTile<T>::lds_bytes(h->nz), s, view<T>(h, l), b, x, xc, par, ncol_c,
+                       y, T(h->cfg.omega), batch, active, sweep_mid(h->nz));
+    if (prof)  // b, x, kh[2], cc, mm read; x_new written
+        prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE, 7.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
 }
 
 template <typename T, int MODE>
 void launch_sweep_m(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
                     int batch, const int* active, hipStream_t s) {
-    const int nz = h->nz;
-#define HH_SWEEP_BUCKET(NZB)                                                     \
-    if (nz <= NZB) {                                                             \
-        launch_sweep_b<T, NZB, MODE>(h, l, b, x, xc, y, batch, active, s);       \
-        return;                                                                  \
+    const int jn = (h->nz + SweepTile<T>::KG - 1) / SweepTile<T>::KG;
+#define HH_SWEEP_BUCKET(J)                                                   \
+    if (jn <= J) {                                                           \
+        launch_sweep_b<T, J, MODE>(h, l, b, x, xc, y, batch, active, s);     \
+        return;                                                              \
     }
-    HH_SWEEP_BUCKET(8)
-    HH_SWEEP_BUCKET(16)
-    HH_SWEEP_BUCKET(32)
-    HH_SWEEP_BUCKET(48)
-    HH_SWEEP_BUCKET(72)
-    HH_SWEEP_BUCKET(96)
-    HH_SWEEP_BUCKET(128)
+    HH_SWEEP_BUCKET(1)
+    HH_SWEEP_BUCKET(2)
+    HH_SWEEP_BUCKET(4)
+    HH_SWEEP_BUCKET(9)
+    HH_SWEEP_BUCKET(15)
 #undef HH_SWEEP_BUCKET
 }
 
@@ -257,12 +314,15 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, bool
     const int ntile = (v.ncol + kBlock - 1) / kBlock;
     const int nkc = (h->nz + kApplyChunk - 1) / kApplyChunk;
     const dim3 grid(ntile * nkc * batch);
+    const bool prof = (l == 0 && sizeof(T) == 8) && prof_begin(h, HELMHOLTZ_PROF_APPLY_FINE, s);
     if (dot)
-        hipLaunchKernelGGL((k_apply<T, true>), grid, dim3(kBlock), 0, s, view<T>(h, l), x, y,
-                           batch, kApplyChunk, nkc, h->partial, h->pstride, active);
+        hipLaunchKernelGGL((k_apply<T, true, kApplyChunk>), grid, dim3(kBlock), 0, s,
+                           view<T>(h, l), x, y, batch, nkc, h->partial, h->pstride, active);
     else
-        hipLaunchKernelGGL((k_apply<T, false>), grid, dim3(kBlock), 0, s, view<T>(h, l), x, y,
-                           batch, kApplyChunk, nkc, nullptr, 0, active);
+        hipLaunchKernelGGL((k_apply<T, false, kApplyChunk>), grid, dim3(kBlock), 0, s,
+                           view<T>(h, l), x, y, batch, nkc, nullptr, 0, active);
+    if (prof)  // x, kh[2], kv, delta read; y written
+        prof_end(h, HELMHOLTZ_PROF_APPLY_FINE, 6.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
 }
 
 // ---- V-cycle (Algorithm 1) ------------------------------------------------
@@ -465,7 +525,7 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
     for (int l = 0; l < h->L; ++l) {
         Level& v = h->lev[l];
         hipLaunchKernelGGL(k_factor, dim3((v.ncol + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
-                           view<double>(h, l), nz, v.d.cc, v.d.mm);
+                           view<double>(h, l), sweep_mid(nz), v.d.cc, v.d.mm);
         // float32 copies, rounded once from float64 (kh, kv, dl, cc, mm are
         // contiguous in both precisions)
         const int64_t nv = int64_t(nz) * v.ncol;
@@ -485,8 +545,30 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
     return HELMHOLTZ_OK;
 }
 
+int helmholtz_profile_enable(helmholtz_t h, int enable) {
+    if (!h) return HELMHOLTZ_EINVAL;
+    for (int k = 0; k < HELMHOLTZ_PROF_COUNT; ++k) {
+        if (int e = prof_flush(h, k)) return e;
+        h->prof[k].ms = h->prof[k].bytes = 0.0;
+        h->prof[k].launches = 0;
+    }
+    h->prof_on = enable != 0;
+    return HELMHOLTZ_OK;
+}
+
+int helmholtz_profile_read(helmholtz_t h, int32_t kernel, double* ms, int64_t* launches,
+                           double* bytes) {
+    if (!h || kernel < 0 || kernel >= HELMHOLTZ_PROF_COUNT) return HELMHOLTZ_EINVAL;
+    if (int e = prof_flush(h, kernel)) return e;
+    if (ms) *ms = h->prof[kernel].ms;
+    if (launches) *launches = h->prof[kernel].launches;
+    if (bytes) *bytes = h->prof[kernel].bytes;
+    return HELMHOLTZ_OK;
+}
+
 int helmholtz_destroy(helmholtz_t h) {
     if (!h) return HELMHOLTZ_EINVAL;
+    for (int k = 0; k < HELMHOLTZ_PROF_COUNT; ++k) (void)prof_flush(h, k);
     if (h->hsc) (void)hipHostFree(h->hsc);
     delete h;
     return HELMHOLTZ_OK;

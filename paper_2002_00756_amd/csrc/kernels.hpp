@@ -21,9 +21,11 @@
 // (e_{k-1} + kv_{k-1}), pivot p_k = e_k + kv_k. Stored: mm_k = 1/p_k and
 // cc_k = kv_k / p_k, so that forward elimination is t_k = r_k + cc_{k-1} t_{k-1}
 // and back substitution is z_k = mm_k t_k + cc_k z_{k+1}.
-// A "twisted" split at row `mid` factors rows below mid bottom-up instead
-// (f, q = f + kv_{k-1}, cc_k = kv_{k-1}/q_k) and row mid with both
-// neighbours eliminated; with mid = nz it is the plain top-down form.
+// The smoother uses a "twisted" split at row mid = nz / 2: rows above mid
+// are factored top-down as above, rows below mid bottom-up (f_{nz-1} =
+// s_{nz-1}, f_k = s_k + kv_k f_{k+1} / (f_{k+1} + kv_k), q_k = f_k + kv_{k-1},
+// mm_k = 1/q_k, cc_k = kv_{k-1}/q_k) and row mid with both neighbours
+// eliminated, so two lanes per column share the sequential work.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -56,8 +58,7 @@ struct LevelView {
 };
 
 // ---------------------------------------------------------------------------
-// Block-Jacobi sweep (Eq. jacobi), one lane per column, whole column in
-// registers (NZMAX >= nz compile-time bound):
+// Block-Jacobi sweep (Eq. jacobi):
 //   x_new = x + omega Hz^-1 (b - H x)
 //         = (1 - omega) x + omega Hz^-1 (b + sum_d K_d x_nbr(d))
 // since H - Hz keeps only the horizontal off-diagonal couplings. The second
@@ -66,29 +67,65 @@ struct LevelView {
 // Modes: kZero x = 0 (first sweep of a level), kPlain, kProlong x += P xc
 // (first post-smoothing sweep, Algorithm 1 prolongation fused in),
 // kProlongZero x = P xc.
+//
+// One workgroup (256 threads) owns a tile of TC columns and all nz levels.
+// The memory-bound work is split from the sequential column recurrence:
+//   1. all threads: for their levels k (k = kg, kg+KG, ...), gather the
+//      right-hand side b + sum K x_nbr and the factor cc into LDS (coalesced
+//      row loads, many independent loads in flight; own x kept in registers);
+//   2. one lane per column eliminates top-down over rows [0, mid) and another
+//      bottom-up over rows (mid, nz) (the twisted factorisation), from LDS;
+//   3. all threads: scale by the pivot reciprocal mm (row mid combines both
+//      eliminations);
+//   4. the two lanes back-substitute outwards from row mid;
+//   5. all threads: x_new = (1 - omega) x + omega z, coalesced stores.
+// TC = 32 columns and KG = 8 level groups per 256-thread workgroup (a wave
+// instruction touches two rows of 128 (float) or 256 (double) contiguous
+// bytes); the small LDS footprint lets up to 8 workgroups share a CU.
 enum SweepMode { kZero = 0, kPlain = 1, kProlong = 2, kProlongZero = 3 };
 
-template <typename T, int NZMAX, int MODE>
-__global__ void __launch_bounds__(kBlock)
+template <typename T, int TC_ = 32, int NT_ = kBlock>
+struct SweepTile {
+    static constexpr int TC = TC_;  // columns per workgroup
+    static constexpr int NT = NT_;  // threads per workgroup
+    static constexpr int KG = NT / TC;
+    static size_t lds_bytes(int nz) { return size_t(2 * nz + 2) * TC * sizeof(T); }
+};
+
+template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = kBlock,
+          int CH_ = 0>
+__global__ void __launch_bounds__(NT)
 k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         const T* __restrict__ xc, const int32_t* __restrict__ parent, int ncol_c,
-        T* __restrict__ y, T omega, int batch, const int* __restrict__ active) {
+        T* __restrict__ y, T omega, int batch, const int* __restrict__ active, int mid) {
+    constexpr int TC = TC_, KG = NT / TC;
+    constexpr int BOT = (TC + 63) / 64 * 64;  // first lane of the bottom elimination (own wave)
+    static_assert(BOT + TC <= NT, "two elimination lane groups must fit the workgroup");
     constexpr bool kHasX = MODE == kPlain || MODE == kProlong;
     constexpr bool kHasP = MODE == kProlong || MODE == kProlongZero;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* R = reinterpret_cast<T*>(smem_raw);  // [nz][TC]: rhs, then t, u, z
+    const int ncol = L.ncol, nz = L.nz;
+    T* Cf = R + nz * TC;                    // [nz][TC]: cc
+    T* E1 = Cf + nz * TC;                   // [TC]: cc_{mid-1} t_{mid-1}
+    T* E2 = E1 + TC;                        // [TC]: cc_{mid+1} t_{mid+1}
+
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % batch, tile = lb / batch;
     if (active && !active[rhs]) return;
-    const int ncol = L.ncol, nz = L.nz;
-    const int c = tile * kBlock + threadIdx.x;
-    if (c >= ncol) return;
+    const int tid = threadIdx.x;
+    const int lc = tid % TC, kg = tid / TC;
+    const int c = tile * TC + lc;
+    const bool valid = c < ncol;
     const int64_t nv = int64_t(nz) * ncol;
     b += rhs * nv;
     y += rhs * nv;
     if (kHasX) x += rhs * nv;
     if (kHasP) xc += rhs * int64_t(nz) * ncol_c;
 
+    // ---- phase 1: right-hand side and factors into LDS --------------------
     int nb[4] = {0, 0, 0, 0}, pn[5] = {0, 0, 0, 0, 0}, fW = 0, fS = 0;
-    if (MODE != kZero) {
+    if (MODE != kZero && valid) {
 #pragma unroll
         for (int d = 0; d < 4; ++d) nb[d] = L.nbr[d * ncol + c];
         fW = L.fface[c];
@@ -105,66 +142,131 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         if (kHasP) v += xc[int64_t(k) * ncol_c + pcol];
         return v;
     };
-
-    T u[NZMAX], cz[NZMAX], xo[NZMAX];
-    T tprev = T(0), cprev = T(0);
+    // Loads of CH levels are issued together before any is used, so each
+    // thread keeps several rows of independent loads in flight.
+    constexpr int CH = CH_ > 0 ? CH_ : (MODE == kZero ? 8 : (kHasP || sizeof(T) == 8 ? 2 : 3));
+    T xo[JMAX], mo[JMAX];
 #pragma unroll
-    for (int k = 0; k < NZMAX; ++k) {
-        if (k < nz) {
-            const int64_t row = int64_t(k) * ncol;
-            T r = b[row + c];
-            T xown = T(0);
-            if (MODE != kZero) {
-                const T* kh = L.kh + 2 * row;
-                const T xE = xv(k, nb[0], pn[0]), xW = xv(k, nb[1], pn[1]);
-                const T xN = xv(k, nb[2], pn[2]), xS = xv(k, nb[3], pn[3]);
-                xown = xv(k, c, pn[4]);
-                r += kh[c] * xE + kh[fW] * xW + kh[ncol + c] * xN + kh[fS] * xS;
+    for (int j0 = 0; j0 < JMAX; j0 += CH) {
+        T vb[CH], vc[CH], vm[CH], vx[CH][5], vk[CH][4];
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+            const int j = j0 + jj;
+            const int k = kg + j * KG;
+            vb[jj] = vc[jj] = vm[jj] = T(0);
+#pragma unroll
+            for (int d = 0; d < 5; ++d) vx[jj][d] = T(0);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) vk[jj][d] = T(0);
+            if (j < JMAX && k < nz && valid) {
+                const int64_t row = int64_t(k) * ncol;
+                vb[jj] = b[row + c];
+                vc[jj] = L.cc[row + c];
+                vm[jj] = L.mm[row + c];
+                if (MODE != kZero) {
+                    const T* kh = L.kh + 2 * row;
+                    vk[jj][0] = kh[c];
+                    vk[jj][1] = kh[fW];
+                    vk[jj][2] = kh[ncol + c];
+                    vk[jj][3] = kh[fS];
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) vx[jj][d] = xv(k, nb[d], pn[d]);
+                    vx[jj][4] = xv(k, c, pn[4]);
+                }
             }
-            const T ck = L.cc[row + c];
-            const T mk = L.mm[row + c];
-            const T t = r + cprev * tprev;
-            u[k] = mk * t;
-            cz[k] = ck;
-            xo[k] = xown;
-            tprev = t;
-            cprev = ck;
+        }
+#pragma unroll
+        for (int jj = 0; jj < CH; ++jj) {
+            const int j = j0 + jj;
+            const int k = kg + j * KG;
+            if (j < JMAX && k < nz) {
+                T r = vb[jj];
+                if (MODE != kZero)
+                    r += vk[jj][0] * vx[jj][0] + vk[jj][1] * vx[jj][1] + vk[jj][2] * vx[jj][2] +
+                         vk[jj][3] * vx[jj][3];
+                xo[j] = vx[jj][4];
+                mo[j] = vm[jj];
+                R[k * TC + lc] = r;
+                Cf[k * TC + lc] = vc[jj];
+            }
         }
     }
-    const T om = omega, om1 = T(1) - omega;
-    T z = T(0);
+    __syncthreads();
+
+    // ---- phase 2: eliminate towards row mid -------------------------------
+    if (tid < TC) {
+        T t = T(0), cp = T(0);
+#pragma unroll 4
+        for (int k = 0; k < mid; ++k) {
+            t = R[k * TC + tid] + cp * t;
+            R[k * TC + tid] = t;
+            cp = Cf[k * TC + tid];
+        }
+        E1[tid] = cp * t;
+    } else if (tid >= BOT && tid < BOT + TC) {
+        const int l2 = tid - BOT;
+        T t = T(0), cn = T(0);
+#pragma unroll 4
+        for (int k = nz - 1; k > mid; --k) {
+            t = R[k * TC + l2] + cn * t;
+            R[k * TC + l2] = t;
+            cn = Cf[k * TC + l2];
+        }
+        E2[l2] = cn * t;
+    }
+    __syncthreads();
+
+    // ---- phase 3: pivot reciprocals (row mid takes both eliminations) ------
 #pragma unroll
-    for (int k = NZMAX - 1; k >= 0; --k) {
+    for (int j = 0; j < JMAX; ++j) {
+        const int k = kg + j * KG;
         if (k < nz) {
-            z = u[k] + cz[k] * z;
-            y[int64_t(k) * ncol + c] = (MODE == kZero) ? om * z : om1 * xo[k] + om * z;
+            const T m = mo[j];
+            T v = R[k * TC + lc];
+            if (k == mid) v += E1[lc] + E2[lc];
+            R[k * TC + lc] = m * v;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: back substitution outwards from row mid ----------------
+    if (tid < TC) {
+        T z = R[mid * TC + tid];
+#pragma unroll 4
+        for (int k = mid - 1; k >= 0; --k) {
+            z = R[k * TC + tid] + Cf[k * TC + tid] * z;
+            R[k * TC + tid] = z;
+        }
+    } else if (tid >= BOT && tid < BOT + TC) {
+        const int l2 = tid - BOT;
+        T z = R[mid * TC + l2];
+#pragma unroll 4
+        for (int k = mid + 1; k < nz; ++k) {
+            z = R[k * TC + l2] + Cf[k * TC + l2] * z;
+            R[k * TC + l2] = z;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 5: relaxation and store -------------------------------------
+    if (!valid) return;
+    const T om = omega, om1 = T(1) - omega;
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+        const int k = kg + j * KG;
+        if (k < nz) {
+            const T z = R[k * TC + lc];
+            y[int64_t(k) * ncol + c] = (MODE == kZero) ? om * z : om1 * xo[j] + om * z;
         }
     }
 }
 
 // ---------------------------------------------------------------------------
 // Operator apply y = H x in flux form (no cancellation of the large vertical
-// couplings against the diagonal). One thread per (column, chunk of levels);
-// keeps x[k-1], x[k], x[k+1] of its column in registers.
+// couplings against the diagonal). One thread per (column, chunk of KC
+// levels); all loads of the chunk are issued before any arithmetic.
 // DOT additionally writes per-block partial sums of x . y (float64) for the
 // Krylov loop.
-template <typename T>
-__device__ __forceinline__ T flux_apply_row(const LevelView<T>& L, const T* __restrict__ x,
-                                            int k, int c, const int nb[4], int fW, int fS,
-                                            T xdn, T xo, T xup, T kvdn) {
-    const int ncol = L.ncol;
-    const int64_t row = int64_t(k) * ncol;
-    const T* kh = L.kh + 2 * row;
-    T y = L.dl[row + c] * xo;
-    y += kh[c] * (xo - x[row + nb[0]]);
-    y += kh[fW] * (xo - x[row + nb[1]]);
-    y += kh[ncol + c] * (xo - x[row + nb[2]]);
-    y += kh[fS] * (xo - x[row + nb[3]]);
-    y += L.kv[row + c] * (xo - xup);
-    y += kvdn * (xo - xdn);
-    return y;
-}
-
 // Sum over the block; the result is valid in thread 0. Fixed order, so
 // repeated runs give identical bits.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
@@ -181,10 +283,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
-template <typename T, bool DOT>
+template <typename T, bool DOT, int KC>
 __global__ void __launch_bounds__(kBlock)
-k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, int kchunk,
-        int nkc, double* __restrict__ partial, int pstride, const int* __restrict__ active) {
+k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, int nkc,
+        double* __restrict__ partial, int pstride, const int* __restrict__ active) {
     __shared__ double sh[kBlock / 64];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % batch, rest = lb / batch;
@@ -202,18 +304,50 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
 #pragma unroll
         for (int d = 0; d < 4; ++d) nb[d] = L.nbr[d * ncol + c];
         const int fW = L.fface[c], fS = L.fface[ncol + c];
-        const int k0 = kc * kchunk, k1 = min(nz, k0 + kchunk);
-        T xdn = k0 > 0 ? x[int64_t(k0 - 1) * ncol + c] : T(0);
-        T kvdn = k0 > 0 ? L.kv[int64_t(k0 - 1) * ncol + c] : T(0);
-        T xo = x[int64_t(k0) * ncol + c];
-        for (int k = k0; k < k1; ++k) {
-            const T xup = (k + 1 < nz) ? x[int64_t(k + 1) * ncol + c] : T(0);
-            const T v = flux_apply_row(L, x, k, c, nb, fW, fS, xdn, xo, xup, kvdn);
-            y[int64_t(k) * ncol + c] = v;
-            if (DOT) acc += double(xo) * double(v);
-            kvdn = L.kv[int64_t(k) * ncol + c];
-            xdn = xo;
-            xo = xup;
+        const int k0 = kc * KC;
+        // all loads of the chunk are issued before any is used
+        T xc[KC + 2], kvv[KC + 1], dl[KC], xn[KC][4], kh[KC][4];
+#pragma unroll
+        for (int j = 0; j < KC + 2; ++j) {
+            const int k = k0 - 1 + j;
+            xc[j] = (k >= 0 && k < nz) ? x[int64_t(k) * ncol + c] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < KC + 1; ++j) {
+            const int k = k0 - 1 + j;
+            kvv[j] = (k >= 0 && k < nz) ? L.kv[int64_t(k) * ncol + c] : T(0);
+        }
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const int k = k0 + j;
+            dl[j] = T(0);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) xn[j][d] = kh[j][d] = T(0);
+            if (k < nz) {
+                const int64_t row = int64_t(k) * ncol;
+                const T* khr = L.kh + 2 * row;
+                dl[j] = L.dl[row + c];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) xn[j][d] = x[row + nb[d]];
+                kh[j][0] = khr[c];
+                kh[j][1] = khr[fW];
+                kh[j][2] = khr[ncol + c];
+                kh[j][3] = khr[fS];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < KC; ++j) {
+            const int k = k0 + j;
+            if (k < nz) {
+                const T xo = xc[j + 1];
+                T v = dl[j] * xo;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
+                v += kvv[j + 1] * (xo - xc[j + 2]);
+                v += kvv[j] * (xo - xc[j]);
+                y[int64_t(k) * ncol + c] = v;
+                if (DOT) acc += double(xo) * double(v);
+            }
         }
     }
     if (DOT) {
@@ -224,9 +358,14 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
 
 // ---------------------------------------------------------------------------
 // Residual and restriction fused (Algorithm 1): bc[k][C] = sum over the four
-// children ch of C of (b - H x)[k][ch], summed in the child order
-// (0,0),(1,0),(0,1),(1,1). The sum has no averaging factor: restriction is the
-// dual of injection (Section 3.6). ZEROX: x = 0, so bc = R b.
+// children ch of C of (b - H x)[k][ch]. The sum has no averaging factor:
+// restriction is the dual of injection (Section 3.6). In that sum the flux
+// through each of the four faces between siblings enters twice with opposite
+// signs, so only the eight faces on the boundary of the coarse cell are
+// evaluated:
+//   bc = sum b - sum delta x - sum_{8 outer faces} K (x_in - x_out)
+//        - sum over children of the vertical fluxes.
+// One thread per (coarse column, chunk of KC levels); ZEROX: x = 0, bc = R b.
 template <typename T, bool ZEROX>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
@@ -255,27 +394,58 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
         }
         return;
     }
-    int nb[4][4], fW[4], fS[4];
+    // outer faces (outside column, stored face index), two per child in child order:
+    //   child (0,0): W, S   child (1,0): E, S   child (0,1): W, N   child (1,1): E, N
+    int out[8], fc[8];
+    {
+        const int c00 = ch[0], c10 = ch[1], c01 = ch[2], c11 = ch[3];
+        out[0] = F.nbr[1 * ncol + c00]; fc[0] = F.fface[c00];
+        out[1] = F.nbr[3 * ncol + c00]; fc[1] = F.fface[ncol + c00];
+        out[2] = F.nbr[0 * ncol + c10]; fc[2] = c10;
+        out[3] = F.nbr[3 * ncol + c10]; fc[3] = F.fface[ncol + c10];
+        out[4] = F.nbr[1 * ncol + c01]; fc[4] = F.fface[c01];
+        out[5] = F.nbr[2 * ncol + c01]; fc[5] = ncol + c01;
+        out[6] = F.nbr[0 * ncol + c11]; fc[6] = c11;
+        out[7] = F.nbr[2 * ncol + c11]; fc[7] = ncol + c11;
+    }
+    T xdn[4], xo[4], kvdn[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-#pragma unroll
-        for (int d = 0; d < 4; ++d) nb[s][d] = F.nbr[d * ncol + ch[s]];
-        fW[s] = F.fface[ch[s]];
-        fS[s] = F.fface[ncol + ch[s]];
+        xdn[s] = k0 > 0 ? x[int64_t(k0 - 1) * ncol + ch[s]] : T(0);
+        kvdn[s] = k0 > 0 ? F.kv[int64_t(k0 - 1) * ncol + ch[s]] : T(0);
+        xo[s] = x[int64_t(k0) * ncol + ch[s]];
     }
     for (int k = k0; k < k1; ++k) {
         const int64_t row = int64_t(k) * ncol;
-        T r[4];
+        const T* kh = F.kh + 2 * row;
+        T xup[4], vb[4], vd[4], vkv[4], vxo[8], vk[8];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
-            const int cs = ch[s];
-            const T xo = x[row + cs];
-            const T xdn = k > 0 ? x[row - ncol + cs] : T(0);
-            const T xup = k + 1 < nz ? x[row + ncol + cs] : T(0);
-            const T kvdn = k > 0 ? F.kv[row - ncol + cs] : T(0);
-            r[s] = b[row + cs] - flux_apply_row(F, x, k, cs, nb[s], fW[s], fS[s], xdn, xo, xup, kvdn);
+            xup[s] = (k + 1 < nz) ? x[row + ncol + ch[s]] : T(0);
+            vb[s] = b[row + ch[s]];
+            vd[s] = F.dl[row + ch[s]];
+            vkv[s] = F.kv[row + ch[s]];
         }
-        bc[int64_t(k) * ncol_c + C] = ((r[0] + r[1]) + r[2]) + r[3];
+#pragma unroll
+        for (int f = 0; f < 8; ++f) {
+            vxo[f] = x[row + out[f]];
+            vk[f] = kh[fc[f]];
+        }
+        T acc = ((vb[0] + vb[1]) + vb[2]) + vb[3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            acc -= vd[s] * xo[s];
+            acc -= vkv[s] * (xo[s] - xup[s]) + kvdn[s] * (xo[s] - xdn[s]);
+        }
+#pragma unroll
+        for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
+        bc[int64_t(k) * ncol_c + C] = acc;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            xdn[s] = xo[s];
+            xo[s] = xup[s];
+            kvdn[s] = vkv[s];
+        }
     }
 }
 
@@ -433,6 +603,7 @@ k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restri
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
     double acc = 0.0;
+#pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const double v = b[off + i];
         x[off + i] = 0.0;
@@ -458,6 +629,7 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ 
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
     double acc = 0.0;
+#pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
         x[off + i] += alpha * p[off + i];
         const double v = r[off + i] - alpha * q[off + i];
@@ -482,6 +654,7 @@ k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
     double a1 = 0.0, a2 = 0.0;
+#pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const double zv = double(z[off + i]);
         a1 += r[off + i] * zv;
@@ -507,6 +680,7 @@ k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
     int64_t i0, i1;
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
+#pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const double zv = double(z[off + i]);
         p[off + i] = init ? zv : zv + beta * p[off + i];

@@ -153,6 +153,18 @@ class Operator:
         _lib.check(code, "helmholtz_solve", allow_not_converged=True)
         return SolveResult(x[0] if sq else x, list(iters), list(rel), code == _lib.OK)
 
+    def profile(self, enable: bool = True):
+        """Start (and reset) or stop the library's kernel timing hook."""
+        _lib.check(self.lib.helmholtz_profile_enable(self._h, int(enable)), "profile_enable")
+
+    def profile_read(self, kernel: int):
+        """``(device ms, launches, algorithmic bytes)`` accumulated for one profiled kernel."""
+        ms, n, by = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        _lib.check(self.lib.helmholtz_profile_read(self._h, kernel, ctypes.byref(ms),
+                                                   ctypes.byref(n), ctypes.byref(by)),
+                   "profile_read")
+        return ms.value, n.value, by.value
+
     def face_grad(self, lam, x):
         """Coefficient gradients of L = g . x given lam = H^-1 g, summed over the batch."""
         lam, _ = self._vec(lam)

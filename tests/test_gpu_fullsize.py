@@ -1,0 +1,72 @@
+"""GPU parity at the benchmark's full size, C192 x 70 (15,482,880 unknowns), in
+the launch configuration the benchmark times (6 levels, 2/2 sweeps, omega 0.8,
+4 coarse sweeps). The oracle runs on the host at this size too (about 30 s)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import helmholtz, mesh, multigrid
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c192():
+    from paper_2002_00756_amd import Operator
+    w = workloads.C192x70
+    print("building C192x70 oracle hierarchy and operators", flush=True)
+    kh, kv, delta = workloads.workload_coefficients(w)
+    levels, parents, childs = mesh.hierarchy(w.N, w.nlevels)
+    hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta)
+    dev = torch.device("cuda")
+    op64 = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp64", device=dev)
+    op32 = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", device=dev)
+    return w, hier, op64, op32
+
+
+def _rel(a, ref):
+    return float(np.abs(a - ref).max() / np.abs(ref).max())
+
+
+def test_apply_full_size(c192):
+    w, hier, op64, _ = c192
+    x = workloads.rhs(w.N, w.nz, seed=5)[0]
+    y = op64.apply(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert _rel(y, hier.apply(0, x)) <= 1e-12
+
+
+def test_vcycle_full_size(c192):
+    """Float64 V-cycle to 1e-10; float32 V-cycle within the float32 bound of 1e-3."""
+    w, hier, op64, op32 = c192
+    print("oracle V-cycle at C192x70", flush=True)
+    b = workloads.rhs(w.N, w.nz)[0]
+    ref = multigrid.vcycle(hier, b)
+    bd = torch.from_numpy(b).cuda()
+    z64 = op64.vcycle(bd).cpu().numpy()
+    z32 = op32.vcycle_f32(bd.float()).double().cpu().numpy()
+    assert _rel(z64, ref) <= 1e-10
+    assert _rel(z32, ref) <= 1e-3
+
+
+def test_mixed_solve_full_size_manufactured(c192):
+    """x* ~ N(0,1), b = H x* by the oracle; float32-MG CG to 1e-6.
+
+    Gate: true float64 residual (oracle apply) <= 1.05e-6 relative, same
+    iteration count as the float64 path +-1; the error against x* is printed.
+    """
+    w, hier, op64, op32 = c192
+    xs = workloads.rhs(w.N, w.nz, seed=9)[0]
+    b = hier.apply(0, xs)
+    bd = torch.from_numpy(b).cuda()
+    r32 = op32.solve(bd, rtol=1e-6)
+    r64 = op64.solve(bd, rtol=1e-6)
+    assert r32.converged and r64.converged
+    assert abs(r32.iters[0] - r64.iters[0]) <= 1
+    x = r32.x.cpu().numpy()
+    true = np.linalg.norm(b - hier.apply(0, x)) / np.linalg.norm(b)
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    print(f"mixed: iters {r32.iters[0]} (fp64 {r64.iters[0]}), true relres {true:.2e}, "
+          f"error vs x* {err:.2e}", flush=True)
+    assert true <= 1.05e-6
+    assert err <= 1e-4

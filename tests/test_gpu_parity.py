@@ -48,7 +48,7 @@ CASES = [
     (4, 3, 3, 5.0, 1000.0, False),
     (24, 30, 4, 1.0, 1000.0, True),
     (6, 70, 2, 1.0, 1000.0, True),
-    (16, 100, 5, 2.0, 10.0, False),
+    (16, 120, 5, 2.0, 10.0, False),
 ]
 
 
