@@ -17,6 +17,7 @@ adjoint (backward) step and the oracle on the host CPU are reported beside it.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -69,6 +70,28 @@ def cg_bytes_per_unknown(vc_words, mixed, flexible):
     dot = 8 + zsz + (8 if flexible else 0)
     pupd = zsz + 8 + 8
     return apply_dot + update + vc + dot + pupd
+
+
+def kernel_sources_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "helmholtz.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2002_00756_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path):
+    """HBM bytes per launch of the profiled kernel from the committed counter summary,
+    or None if there is none or the kernel sources changed since it was taken."""
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip("# ").strip()] = v.strip()
+    if vals.get("kernel sources sha256 prefix") != kernel_sources_hash():
+        return None
+    return float(vals["traffic bytes/dispatch"])
 
 
 def cpu_model():
@@ -242,10 +265,7 @@ def main():
     # --- dominant kernel: fine-level float32 smoothing sweep -----------------
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
     achieved = (sweep_bytes / max(sweep_n, 1)) / (sweep_avg_ms * 1e-3) / 1e9
-    traffic = None
-    tfile = os.path.join(ROOT, "profiles", "traffic_sweep_f32_C192x70.json")
-    if os.path.exists(tfile):
-        traffic = json.load(open(tfile)).get("bytes_per_launch")
+    traffic = measured_traffic(os.path.join(ROOT, "profiles", "traffic_sweep_f32_C192x70.txt"))
 
     per_iter32 = cg_bytes_per_unknown(words, True, args.cg == "flexible")
     per_iter64 = cg_bytes_per_unknown(words, False, False)

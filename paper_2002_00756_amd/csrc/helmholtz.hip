@@ -248,17 +248,17 @@ LevelData<T>& data(helmholtz_s* h, int l) {
 // ---- sweep launch: compile-time bound on levels per thread ---------------
 inline int sweep_mid(int nz) { return nz / 2; }
 
-template <typename T, int JMAX, int MODE>
+template <typename T, int JMAX, int MODE, int NT>
 void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
                     int batch, const int* active, hipStream_t s) {
     const Level& v = h->lev[l];
-    constexpr int TC = SweepTile<T>::TC;
-    const int ntile = (v.ncol + TC - 1) / TC;
+    using Tile = SweepTile<T, 32, NT>;
+    const int ntile = (v.ncol + Tile::TC - 1) / Tile::TC;
     const int32_t* par = (l + 1 < h->L) ? v.parent : nullptr;
     const int ncol_c = (l + 1 < h->L) ? h->lev[l + 1].ncol : 0;
     const bool prof = (l == 0 && MODE == kPlain) && prof_begin(h, HELMHOLTZ_PROF_SWEEP_FINE, s);
-    hipLaunchKernelGGL((k_sweep<T, JMAX, MODE>), dim3(ntile * batch), dim3(kBlock),
-                       SweepTile<T>::lds_bytes(h->nz), s, view<T>(h, l), b, x, xc, par, ncol_c,
+    hipLaunchKernelGGL((k_sweep<T, JMAX, MODE, Tile::TC, NT>), dim3(ntile * batch), dim3(NT),
+                       Tile::lds_bytes(h->nz), s, view<T>(h, l), b, x, xc, par, ncol_c,
                        y, T(h->cfg.omega), batch, active, sweep_mid(h->nz));
     if (prof)  // b, x, kh[2], cc, mm read; x_new written
         prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE, 7.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
@@ -267,11 +267,12 @@ void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T
 template <typename T, int MODE>
 void launch_sweep_m(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
                     int batch, const int* active, hipStream_t s) {
-    const int jn = (h->nz + SweepTile<T>::KG - 1) / SweepTile<T>::KG;
-#define HH_SWEEP_BUCKET(J)                                                   \
-    if (jn <= J) {                                                           \
-        launch_sweep_b<T, J, MODE>(h, l, b, x, xc, y, batch, active, s);     \
-        return;                                                              \
+    constexpr int KG = kBlock / 32;
+    const int jn = (h->nz + KG - 1) / KG;
+#define HH_SWEEP_BUCKET(J)                                                        \
+    if (jn <= J) {                                                                \
+        launch_sweep_b<T, J, MODE, kBlock>(h, l, b, x, xc, y, batch, active, s);  \
+        return;                                                                   \
     }
     HH_SWEEP_BUCKET(1)
     HH_SWEEP_BUCKET(2)
@@ -280,6 +281,10 @@ void launch_sweep_m(const helmholtz_s* h, int l, const T* b, const T* x, const T
     HH_SWEEP_BUCKET(15)
 #undef HH_SWEEP_BUCKET
 }
+
+// Levels too small to fill the GPU are bound by the latency of a few dependent
+// steps per thread; their kernels give each thread less work.
+inline bool small_level(const helmholtz_s* h, int l) { return h->lev[l].ncol < 4096; }
 
 template <typename T>
 void launch_sweep(const helmholtz_s* h, int l, int mode, const T* b, const T* x, const T* xc,
@@ -297,14 +302,16 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
                            const int* active, hipStream_t s) {
     const Level& c = h->lev[l + 1];
     const int ntile = (c.ncol + kBlock - 1) / kBlock;
-    const int nkc = (h->nz + kApplyChunk - 1) / kApplyChunk;
+    // one level per thread on small levels (one dependent step), four otherwise
+    const int kchunk = small_level(h, l) ? 1 : kApplyChunk;
+    const int nkc = (h->nz + kchunk - 1) / kchunk;
     const dim3 grid(ntile * nkc * batch);
     if (x)
         hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, dim3(kBlock), 0, s, view<T>(h, l),
-                           c.child, c.ncol, b, x, bc, batch, kApplyChunk, nkc, active);
+                           c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
     else
         hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, dim3(kBlock), 0, s, view<T>(h, l),
-                           c.child, c.ncol, b, x, bc, batch, kApplyChunk, nkc, active);
+                           c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
 }
 
 template <typename T>
@@ -329,28 +336,40 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, bool
 // Level l smooths b_l into out_l, using tmp_l as the Jacobi ping-pong partner.
 // The writes of x on one level alternate between the two buffers; they are
 // assigned from the last write backwards so that the last lands in out_l.
+// Number of x writes on level l and the buffer that write j goes to: the
+// writes alternate between out_l and tmp_l, assigned from the last one
+// backwards so that the last lands in out_l.
+inline int level_writes(const helmholtz_s* h, int l) {
+    const helmholtz_config& cfg = h->cfg;
+    return l == h->L - 1 ? cfg.n_coarse : cfg.n_pre + std::max(cfg.n_post, 1);
+}
+
+template <typename T>
+T* write_dst(const helmholtz_s* h, int l, int j, T* out, T* tmp) {
+    return ((level_writes(h, l) - 1 - j) % 2 == 0) ? out : tmp;
+}
+
+// Level l smooths b_l into out_l (Algorithm 1), using tmp_l as the Jacobi
+// ping-pong partner.
 template <typename T>
 void vcycle_level(helmholtz_s* h, int l, const T* b, T* out, int batch, const int* active,
                   hipStream_t s) {
     const helmholtz_config& cfg = h->cfg;
     T* tmp = data<T>(h, l).t;
-    const bool coarsest = (l == h->L - 1);
-    if (coarsest) {
-        const int W = cfg.n_coarse;
+    const int W = level_writes(h, l);
+    if (l == h->L - 1) {
         const T* prev = nullptr;
         for (int j = 0; j < W; ++j) {
-            T* dst = ((W - 1 - j) % 2 == 0) ? out : tmp;
+            T* dst = write_dst<T>(h, l, j, out, tmp);
             launch_sweep<T>(h, l, j == 0 ? kZero : kPlain, b, prev, nullptr, dst, batch, active, s);
             prev = dst;
         }
         return;
     }
-    const int W = cfg.n_pre + std::max(cfg.n_post, 1);
     int j = 0;
     const T* prev = nullptr;
-    auto dst_of = [&](int jj) { return ((W - 1 - jj) % 2 == 0) ? out : tmp; };
     for (int i = 0; i < cfg.n_pre; ++i, ++j) {
-        T* dst = dst_of(j);
+        T* dst = write_dst<T>(h, l, j, out, tmp);
         launch_sweep<T>(h, l, j == 0 ? kZero : kPlain, b, prev, nullptr, dst, batch, active, s);
         prev = dst;
     }
@@ -358,7 +377,7 @@ void vcycle_level(helmholtz_s* h, int l, const T* b, T* out, int batch, const in
     launch_resid_restrict<T>(h, l, b, prev, c.b, batch, active, s);
     vcycle_level<T>(h, l + 1, c.b, c.x, batch, active, s);
     if (cfg.n_post == 0) {
-        T* dst = dst_of(j);
+        T* dst = write_dst<T>(h, l, j, out, tmp);
         const Level& v = h->lev[l];
         const int64_t total = int64_t(batch) * h->nz * v.ncol;
         hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(total)), dim3(kBlock), 0, s, v.ncol,
@@ -366,7 +385,7 @@ void vcycle_level(helmholtz_s* h, int l, const T* b, T* out, int batch, const in
         return;
     }
     for (int i = 0; i < cfg.n_post; ++i, ++j) {
-        T* dst = dst_of(j);
+        T* dst = write_dst<T>(h, l, j, out, tmp);
         int mode = kPlain;
         if (i == 0) mode = prev ? kProlong : kProlongZero;
         launch_sweep<T>(h, l, mode, b, prev, c.x, dst, batch, active, s);

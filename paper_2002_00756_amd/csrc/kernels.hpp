@@ -84,6 +84,127 @@ struct LevelView {
 // bytes); the small LDS footprint lets up to 8 workgroups share a CU.
 enum SweepMode { kZero = 0, kPlain = 1, kProlong = 2, kProlongZero = 3 };
 
+// Phases 2-4 of the tile column solve z = Hz^-1 r for the TC columns of a
+// tile: on entry R[k][lc] holds r, Cf[k][lc] the factor cc and mo[j] the
+// pivot reciprocal of level kg + j KG of the calling thread's column; on exit
+// R holds z. Two lanes per column (tid < TC: rows above mid, top-down; BOT <=
+// tid < BOT + TC: rows below mid, bottom-up) walk the column, SEQ levels per
+// LDS round trip; row mid combines both eliminations.
+template <typename T, int TC, int JMAX>
+__device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T (&mo)[JMAX],
+                                             int tid, int lc, int kg, int KG, int BOT, int mid,
+                                             int nz) {
+    // ---- phase 2: eliminate towards row mid -------------------------------
+    // The column walks read SEQ levels into registers, run the recurrence,
+    // then write them back: one LDS round trip per SEQ levels.
+    constexpr int SEQ = 8;
+    if (tid < TC) {
+        T t = T(0), cp = T(0);
+        for (int k0 = 0; k0 < mid; k0 += SEQ) {
+            T rr[SEQ], cf[SEQ];
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                const int k = k0 + i;
+                rr[i] = k < mid ? R[k * TC + tid] : T(0);
+                cf[i] = k < mid ? Cf[k * TC + tid] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                if (k0 + i < mid) {
+                    t = rr[i] + cp * t;
+                    rr[i] = t;
+                    cp = cf[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i)
+                if (k0 + i < mid) R[(k0 + i) * TC + tid] = rr[i];
+        }
+        E1[tid] = cp * t;
+    } else if (tid >= BOT && tid < BOT + TC) {
+        const int l2 = tid - BOT;
+        T t = T(0), cn = T(0);
+        for (int k0 = nz - 1; k0 > mid; k0 -= SEQ) {
+            T rr[SEQ], cf[SEQ];
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                const int k = k0 - i;
+                rr[i] = k > mid ? R[k * TC + l2] : T(0);
+                cf[i] = k > mid ? Cf[k * TC + l2] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                if (k0 - i > mid) {
+                    t = rr[i] + cn * t;
+                    rr[i] = t;
+                    cn = cf[i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i)
+                if (k0 - i > mid) R[(k0 - i) * TC + l2] = rr[i];
+        }
+        E2[l2] = cn * t;
+    }
+    __syncthreads();
+
+    // ---- phase 3: pivot reciprocals (row mid takes both eliminations) ------
+#pragma unroll
+    for (int j = 0; j < JMAX; ++j) {
+        const int k = kg + j * KG;
+        if (k < nz) {
+            T v = R[k * TC + lc];
+            if (k == mid) v += E1[lc] + E2[lc];
+            R[k * TC + lc] = mo[j] * v;
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 4: back substitution outwards from row mid ----------------
+    if (tid < TC) {
+        T z = R[mid * TC + tid];
+        for (int k0 = mid - 1; k0 >= 0; k0 -= SEQ) {
+            T rr[SEQ], cf[SEQ];
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                const int k = k0 - i;
+                rr[i] = k >= 0 ? R[k * TC + tid] : T(0);
+                cf[i] = k >= 0 ? Cf[k * TC + tid] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                z = rr[i] + cf[i] * z;
+                rr[i] = z;
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i)
+                if (k0 - i >= 0) R[(k0 - i) * TC + tid] = rr[i];
+        }
+    } else if (tid >= BOT && tid < BOT + TC) {
+        const int l2 = tid - BOT;
+        T z = R[mid * TC + l2];
+        for (int k0 = mid + 1; k0 < nz; k0 += SEQ) {
+            T rr[SEQ], cf[SEQ];
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                const int k = k0 + i;
+                rr[i] = k < nz ? R[k * TC + l2] : T(0);
+                cf[i] = k < nz ? Cf[k * TC + l2] : T(0);
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i) {
+                z = rr[i] + cf[i] * z;
+                rr[i] = z;
+            }
+#pragma unroll
+            for (int i = 0; i < SEQ; ++i)
+                if (k0 + i < nz) R[(k0 + i) * TC + l2] = rr[i];
+        }
+    }
+    __syncthreads();
+
+}
+
 template <typename T, int TC_ = 32, int NT_ = kBlock>
 struct SweepTile {
     static constexpr int TC = TC_;  // columns per workgroup
@@ -193,60 +314,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     }
     __syncthreads();
 
-    // ---- phase 2: eliminate towards row mid -------------------------------
-    if (tid < TC) {
-        T t = T(0), cp = T(0);
-#pragma unroll 4
-        for (int k = 0; k < mid; ++k) {
-            t = R[k * TC + tid] + cp * t;
-            R[k * TC + tid] = t;
-            cp = Cf[k * TC + tid];
-        }
-        E1[tid] = cp * t;
-    } else if (tid >= BOT && tid < BOT + TC) {
-        const int l2 = tid - BOT;
-        T t = T(0), cn = T(0);
-#pragma unroll 4
-        for (int k = nz - 1; k > mid; --k) {
-            t = R[k * TC + l2] + cn * t;
-            R[k * TC + l2] = t;
-            cn = Cf[k * TC + l2];
-        }
-        E2[l2] = cn * t;
-    }
-    __syncthreads();
-
-    // ---- phase 3: pivot reciprocals (row mid takes both eliminations) ------
-#pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-        const int k = kg + j * KG;
-        if (k < nz) {
-            const T m = mo[j];
-            T v = R[k * TC + lc];
-            if (k == mid) v += E1[lc] + E2[lc];
-            R[k * TC + lc] = m * v;
-        }
-    }
-    __syncthreads();
-
-    // ---- phase 4: back substitution outwards from row mid ----------------
-    if (tid < TC) {
-        T z = R[mid * TC + tid];
-#pragma unroll 4
-        for (int k = mid - 1; k >= 0; --k) {
-            z = R[k * TC + tid] + Cf[k * TC + tid] * z;
-            R[k * TC + tid] = z;
-        }
-    } else if (tid >= BOT && tid < BOT + TC) {
-        const int l2 = tid - BOT;
-        T z = R[mid * TC + l2];
-#pragma unroll 4
-        for (int k = mid + 1; k < nz; ++k) {
-            z = R[k * TC + l2] + Cf[k * TC + l2] * z;
-            R[k * TC + l2] = z;
-        }
-    }
-    __syncthreads();
+    column_solve<T, TC, JMAX>(R, Cf, E1, E2, mo, tid, lc, kg, KG, BOT, mid, nz);
 
     // ---- phase 5: relaxation and store -------------------------------------
     if (!valid) return;
