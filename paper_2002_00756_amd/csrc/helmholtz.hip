@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -96,12 +97,14 @@ struct helmholtz_s {
     double* partial = nullptr;
     double* partial2 = nullptr;
     int pstride = 0;
-    double* sc = nullptr;  // [B][8] scalars
-    int* active = nullptr; // [B]
-    int* flags = nullptr;  // set-up validation bits
-    // pinned host mirror of sc + active + flags
+    double* sc = nullptr;     // [B][8] scalars
+    int* active = nullptr;    // [B]
+    int* flags = nullptr;     // set-up validation bits
+    // pinned, host-coherent mirror written by the device: scalars, flags,
+    // per-RHS sequence numbers; plus the set-up flags
     double* hsc = nullptr;
     int* hact = nullptr;
+    int* hseq = nullptr;
     int* hflags = nullptr;
     size_t ws_bytes = 0;
     // kernel timing hook: event pairs recorded around profiled launches
@@ -229,6 +232,11 @@ void prof_end(const helmholtz_s* h, int kernel, double bytes, hipStream_t s) {
     (void)hipEventRecord(P.stop.back(), s);
 }
 
+CgState cg_state(const helmholtz_s* h) {
+    return CgState{h->partial, h->partial2, h->pstride, h->sc, h->active,
+                   h->hsc,     h->hact,     h->hseq};
+}
+
 template <typename T>
 LevelView<T> view(const helmholtz_s* h, int l) {
     const Level& v = h->lev[l];
@@ -324,10 +332,10 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, bool
     const bool prof = (l == 0 && sizeof(T) == 8) && prof_begin(h, HELMHOLTZ_PROF_APPLY_FINE, s);
     if (dot)
         hipLaunchKernelGGL((k_apply<T, true, kApplyChunk>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), x, y, batch, nkc, h->partial, h->pstride, active);
+                           view<T>(h, l), x, y, batch, nkc, cg_state(h), active);
     else
         hipLaunchKernelGGL((k_apply<T, false, kApplyChunk>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), x, y, batch, nkc, nullptr, 0, active);
+                           view<T>(h, l), x, y, batch, nkc, cg_state(h), active);
     if (prof)  // x, kh[2], kv, delta read; y written
         prof_end(h, HELMHOLTZ_PROF_APPLY_FINE, 6.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
 }
@@ -420,6 +428,36 @@ int precondition(helmholtz_s* h, const double* r, double* z, int batch, bool r32
     return last_error();
 }
 
+// Wait until the device has published sequence number `seq` for every
+// right-hand side with need[i] != 0 (written by the last block of a norm
+// reduction into host-coherent memory). Polls the flags; falls back on the
+// stream state so that a failed launch cannot leave the host spinning.
+int wait_published(helmholtz_s* h, hipStream_t s, const std::vector<int>& need, int seq) {
+    using clock = std::chrono::steady_clock;
+    const auto t0 = clock::now();
+    for (unsigned spin = 1;; ++spin) {
+        bool done = true;
+        for (size_t i = 0; i < need.size(); ++i)
+            if (need[i] && __atomic_load_n(&h->hseq[i], __ATOMIC_ACQUIRE) != seq) {
+                done = false;
+                break;
+            }
+        if (done) return HELMHOLTZ_OK;
+        if (spin % 256 == 0) {
+            const hipError_t q = hipStreamQuery(s);
+            if (q == hipSuccess) {
+                // the stream is idle: the values must be there now
+                for (size_t i = 0; i < need.size(); ++i)
+                    if (need[i] && __atomic_load_n(&h->hseq[i], __ATOMIC_ACQUIRE) != seq)
+                        return HELMHOLTZ_EHIP;
+                return HELMHOLTZ_OK;
+            }
+            if (q != hipErrorNotReady) return HELMHOLTZ_EHIP;
+            if (clock::now() - t0 > std::chrono::seconds(120)) return HELMHOLTZ_EHIP;
+        }
+    }
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -480,14 +518,17 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
         helmholtz_destroy(h);
         return code;
     };
-    if (hipHostMalloc(reinterpret_cast<void**>(&h->hsc), size_t(h->B) * 8 * sizeof(double) +
-                                                             size_t(h->B) * sizeof(int) + 16,
-                      hipHostMallocDefault) != hipSuccess) {
+    // host-coherent pinned memory: the device publishes the CG scalars here
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->hsc),
+                      size_t(h->B) * 8 * sizeof(double) + size_t(h->B) * 2 * sizeof(int) + 16,
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
         h->hsc = nullptr;
         return fail(HELMHOLTZ_EHIP);
     }
     h->hact = reinterpret_cast<int*>(h->hsc + size_t(h->B) * 8);
-    h->hflags = h->hact + h->B;
+    h->hseq = h->hact + h->B;
+    h->hflags = h->hseq + h->B;
+    for (int i = 0; i < h->B; ++i) h->hseq[i] = -1;
 
     // mesh tables of every level, built on the host and copied once
     const int nz = h->nz;
@@ -627,24 +668,22 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     float* r32 = mixed ? h->lev[0].f.b : nullptr;
     float* z32 = mixed ? h->lev[0].f.x : nullptr;
     const dim3 red(kRedBlocks * batch), blk(kBlock);
+    const CgState st = cg_state(h);
 
+    // the host mirror doubles as staging for the initial scalars
     for (int i = 0; i < batch; ++i) {
         for (int j = 0; j < 8; ++j) h->hsc[i * 8 + j] = 0.0;
         h->hsc[i * 8 + kRtol2] = rtol * rtol;
+        __atomic_store_n(&h->hseq[i], -1, __ATOMIC_RELEASE);
     }
     HH_CHECK(hipMemcpyAsync(h->sc, h->hsc, size_t(batch) * 8 * sizeof(double),
                             hipMemcpyHostToDevice, s));
     // x = 0, r = b, ||b||^2
-    hipLaunchKernelGGL(k_cg_init, red, blk, 0, s, b, x, h->r, r32, n, kRedBlocks, h->partial,
-                       h->pstride);
-    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinBB), kRedBlocks, h->partial,
-                       nullptr, h->pstride, h->sc, h->active);
-    HH_CHECK(hipMemcpyAsync(h->hsc, h->sc, size_t(batch) * 8 * sizeof(double),
-                            hipMemcpyDeviceToHost, s));
-    HH_CHECK(hipMemcpyAsync(h->hact, h->active, size_t(batch) * sizeof(int),
-                            hipMemcpyDeviceToHost, s));
-    HH_CHECK(hipStreamSynchronize(s));
+    hipLaunchKernelGGL(k_cg_init, red, blk, 0, s, b, x, h->r, r32, n, kRedBlocks, st);
+    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinBB), kRedBlocks, 0);
     if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
+    std::vector<int> need(batch, 1);
+    if (int e = wait_published(h, s, need, 0)) return e;
     std::vector<double> bnorm2(batch);
     std::vector<int32_t> it(batch, 0);
     std::vector<double> rel(batch, 0.0);
@@ -668,12 +707,11 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     if (int e = precondition(h, h->r, mixed ? nullptr : h->z, batch, true, h->active, s)) return e;
     if (mixed)
         hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, nullptr, n, kRedBlocks,
-                           h->active, h->partial, nullptr, h->pstride);
+                           st);
     else
         hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, nullptr, n,
-                           kRedBlocks, h->active, h->partial, nullptr, h->pstride);
-    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinRho), kRedBlocks, h->partial,
-                       nullptr, h->pstride, h->sc, h->active);
+                           kRedBlocks, st);
+    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinRho), kRedBlocks, 0);
     if (mixed)
         hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks, h->sc,
                            h->active, 1);
@@ -689,19 +727,14 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         for (int i = 0; i < batch; ++i) was_active[i] = h->hact[i];
         // q = H p, alpha = rho / p.q
         launch_apply<double>(h, 0, h->p, h->q, batch, true, h->active, s);
-        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinAlpha), ntile0 * nkc0,
-                           h->partial, nullptr, h->pstride, h->sc, h->active);
-        // x += alpha p, r -= alpha q, ||r||^2, convergence flags
+        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
+                           0);
+        // x += alpha p, r -= alpha q, ||r||^2 and the convergence flags, published
         hipLaunchKernelGGL(k_cg_update, red, blk, 0, s, x, h->r, r32, h->p, h->q, n, kRedBlocks,
-                           h->sc, h->active, h->partial, h->pstride);
-        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(kFinRR), kRedBlocks,
-                           h->partial, nullptr, h->pstride, h->sc, h->active);
-        HH_CHECK(hipMemcpyAsync(h->hsc, h->sc, size_t(batch) * 8 * sizeof(double),
-                                hipMemcpyDeviceToHost, s));
-        HH_CHECK(hipMemcpyAsync(h->hact, h->active, size_t(batch) * sizeof(int),
-                                hipMemcpyDeviceToHost, s));
-        HH_CHECK(hipStreamSynchronize(s));
+                           st);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinRR), kRedBlocks, iter);
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
+        if (int e = wait_published(h, s, was_active, iter)) return e;
         bool still = false;
         for (int i = 0; i < batch; ++i) {
             if (!was_active[i]) continue;
@@ -722,12 +755,12 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         const double* qarg = flex ? h->q : nullptr;
         if (mixed)
             hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, qarg, n, kRedBlocks,
-                               h->active, h->partial, h->partial2, h->pstride);
+                               st);
         else
             hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, qarg, n,
-                               kRedBlocks, h->active, h->partial, h->partial2, h->pstride);
-        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, int(flex ? kFinBetaFlex : kFinBeta),
-                           kRedBlocks, h->partial, h->partial2, h->pstride, h->sc, h->active);
+                               kRedBlocks, st);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st,
+                           int(flex ? kFinBetaFlex : kFinBeta), kRedBlocks, 0);
         if (mixed)
             hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks,
                                h->sc, h->active, 0);
@@ -735,6 +768,8 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
             hipLaunchKernelGGL((k_p_update<double>), red, blk, 0, s, h->z, h->p, n, kRedBlocks,
                                h->sc, h->active, 0);
     }
+    // the caller may read x as soon as this returns on the host
+    HH_CHECK(hipStreamSynchronize(s));
     return finish(status);
 }
 

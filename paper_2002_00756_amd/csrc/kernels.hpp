@@ -84,29 +84,28 @@ struct LevelView {
 // bytes); the small LDS footprint lets up to 8 workgroups share a CU.
 enum SweepMode { kZero = 0, kPlain = 1, kProlong = 2, kProlongZero = 3 };
 
-// Phases 2-4 of the tile column solve z = Hz^-1 r for the TC columns of a
-// tile: on entry R[k][lc] holds r, Cf[k][lc] the factor cc and mo[j] the
-// pivot reciprocal of level kg + j KG of the calling thread's column; on exit
-// R holds z. Two lanes per column (tid < TC: rows above mid, top-down; BOT <=
-// tid < BOT + TC: rows below mid, bottom-up) walk the column, SEQ levels per
-// LDS round trip; row mid combines both eliminations.
-template <typename T, int TC, int JMAX>
+// Phases 2-4 of the column solve z = Hz^-1 r for ncol columns held in LDS
+// with row stride S: on entry R[k*S + col] holds r and Cf[k*S + col] the
+// factor cc; the calling thread owns column lc (if lc < ncol) at levels
+// kg + j KG, whose pivot reciprocals it holds in mo[j]. On exit R holds z.
+// Two lanes per column (tid < ncol: rows above mid, top-down; BOT <= tid <
+// BOT + ncol: rows below mid, bottom-up) walk the column, SEQ levels per LDS
+// round trip; row mid combines both eliminations. E1, E2 hold ncol values.
+template <typename T, int JMAX>
 __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T (&mo)[JMAX],
                                              int tid, int lc, int kg, int KG, int BOT, int mid,
-                                             int nz) {
-    // ---- phase 2: eliminate towards row mid -------------------------------
-    // The column walks read SEQ levels into registers, run the recurrence,
-    // then write them back: one LDS round trip per SEQ levels.
+                                             int nz, int S, int ncol) {
     constexpr int SEQ = 8;
-    if (tid < TC) {
+    // ---- phase 2: eliminate towards row mid -------------------------------
+    if (tid < ncol) {
         T t = T(0), cp = T(0);
         for (int k0 = 0; k0 < mid; k0 += SEQ) {
             T rr[SEQ], cf[SEQ];
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
                 const int k = k0 + i;
-                rr[i] = k < mid ? R[k * TC + tid] : T(0);
-                cf[i] = k < mid ? Cf[k * TC + tid] : T(0);
+                rr[i] = k < mid ? R[k * S + tid] : T(0);
+                cf[i] = k < mid ? Cf[k * S + tid] : T(0);
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
@@ -118,10 +117,10 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i)
-                if (k0 + i < mid) R[(k0 + i) * TC + tid] = rr[i];
+                if (k0 + i < mid) R[(k0 + i) * S + tid] = rr[i];
         }
         E1[tid] = cp * t;
-    } else if (tid >= BOT && tid < BOT + TC) {
+    } else if (tid >= BOT && tid < BOT + ncol) {
         const int l2 = tid - BOT;
         T t = T(0), cn = T(0);
         for (int k0 = nz - 1; k0 > mid; k0 -= SEQ) {
@@ -129,8 +128,8 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
                 const int k = k0 - i;
-                rr[i] = k > mid ? R[k * TC + l2] : T(0);
-                cf[i] = k > mid ? Cf[k * TC + l2] : T(0);
+                rr[i] = k > mid ? R[k * S + l2] : T(0);
+                cf[i] = k > mid ? Cf[k * S + l2] : T(0);
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
@@ -142,34 +141,36 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i)
-                if (k0 - i > mid) R[(k0 - i) * TC + l2] = rr[i];
+                if (k0 - i > mid) R[(k0 - i) * S + l2] = rr[i];
         }
         E2[l2] = cn * t;
     }
     __syncthreads();
 
     // ---- phase 3: pivot reciprocals (row mid takes both eliminations) ------
+    if (lc < ncol) {
 #pragma unroll
-    for (int j = 0; j < JMAX; ++j) {
-        const int k = kg + j * KG;
-        if (k < nz) {
-            T v = R[k * TC + lc];
-            if (k == mid) v += E1[lc] + E2[lc];
-            R[k * TC + lc] = mo[j] * v;
+        for (int j = 0; j < JMAX; ++j) {
+            const int k = kg + j * KG;
+            if (k < nz) {
+                T v = R[k * S + lc];
+                if (k == mid) v += E1[lc] + E2[lc];
+                R[k * S + lc] = mo[j] * v;
+            }
         }
     }
     __syncthreads();
 
     // ---- phase 4: back substitution outwards from row mid ----------------
-    if (tid < TC) {
-        T z = R[mid * TC + tid];
+    if (tid < ncol) {
+        T z = R[mid * S + tid];
         for (int k0 = mid - 1; k0 >= 0; k0 -= SEQ) {
             T rr[SEQ], cf[SEQ];
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
                 const int k = k0 - i;
-                rr[i] = k >= 0 ? R[k * TC + tid] : T(0);
-                cf[i] = k >= 0 ? Cf[k * TC + tid] : T(0);
+                rr[i] = k >= 0 ? R[k * S + tid] : T(0);
+                cf[i] = k >= 0 ? Cf[k * S + tid] : T(0);
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
@@ -178,18 +179,18 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i)
-                if (k0 - i >= 0) R[(k0 - i) * TC + tid] = rr[i];
+                if (k0 - i >= 0) R[(k0 - i) * S + tid] = rr[i];
         }
-    } else if (tid >= BOT && tid < BOT + TC) {
+    } else if (tid >= BOT && tid < BOT + ncol) {
         const int l2 = tid - BOT;
-        T z = R[mid * TC + l2];
+        T z = R[mid * S + l2];
         for (int k0 = mid + 1; k0 < nz; k0 += SEQ) {
             T rr[SEQ], cf[SEQ];
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
                 const int k = k0 + i;
-                rr[i] = k < nz ? R[k * TC + l2] : T(0);
-                cf[i] = k < nz ? Cf[k * TC + l2] : T(0);
+                rr[i] = k < nz ? R[k * S + l2] : T(0);
+                cf[i] = k < nz ? Cf[k * S + l2] : T(0);
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
@@ -198,11 +199,10 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i)
-                if (k0 + i < nz) R[(k0 + i) * TC + l2] = rr[i];
+                if (k0 + i < nz) R[(k0 + i) * S + l2] = rr[i];
         }
     }
     __syncthreads();
-
 }
 
 template <typename T, int TC_ = 32, int NT_ = kBlock>
@@ -314,7 +314,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     }
     __syncthreads();
 
-    column_solve<T, TC, JMAX>(R, Cf, E1, E2, mo, tid, lc, kg, KG, BOT, mid, nz);
+    column_solve<T, JMAX>(R, Cf, E1, E2, mo, tid, lc, kg, KG, BOT, mid, nz, TC, TC);
 
     // ---- phase 5: relaxation and store -------------------------------------
     if (!valid) return;
@@ -351,10 +351,107 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
+// Per right-hand-side scalars sc[rhs*8 + ...]:
+enum { kBB = 0, kRho = 1, kPQ = 2, kAlpha = 3, kRR = 4, kBeta = 5, kZQ = 6, kRtol2 = 7 };
+enum FinalizeMode { kFinBB = 0, kFinRho = 1, kFinAlpha = 2, kFinRR = 3, kFinBeta = 4,
+                    kFinBetaFlex = 5 };
+
+// Reduction state shared by the Krylov kernels. hsc/hact/hseq live in pinned,
+// host-coherent memory: the finalisation of the norm reductions publishes the
+// scalars there and then the sequence number, which the host polls.
+struct CgState {
+    double* partial;   // [B][pstride]
+    double* partial2;  // [B][pstride]
+    int pstride;
+    double* sc;        // [B][8]
+    int* active;       // [B]
+    double* hsc;       // host mirror [B][8]
+    int* hact;         // host mirror [B]
+    int* hseq;         // host mirror [B]
+};
+
+__device__ __forceinline__ void grid_range(int64_t n, int nblk, int blk, int64_t& i0, int64_t& i1) {
+    const int64_t per = (n + nblk - 1) / nblk;
+    i0 = min(n, int64_t(blk) * per);
+    i1 = min(n, i0 + per);
+}
+
+// Sum `cnt` partials in a fixed order (result in every thread).
+__device__ __forceinline__ double reduce_partials(const double* part, int cnt, double* sh) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) acc += part[i];
+    const double s = block_sum(acc, sh);
+    __syncthreads();
+    if (threadIdx.x == 0) sh[0] = s;
+    __syncthreads();
+    return sh[0];
+}
+
+// Store this block's partial sum(s) of a reduction.
+__device__ __forceinline__ void store_partial(const CgState& st, int rhs, int blk, double s1,
+                                              double s2, bool two) {
+    if (threadIdx.x == 0) {
+        st.partial[int64_t(rhs) * st.pstride + blk] = s1;
+        if (two) st.partial2[int64_t(rhs) * st.pstride + blk] = s2;
+    }
+}
+
+// One block per right-hand side: add the `cnt` partials in a fixed order and
+// derive the CG scalar. The norm reductions (kFinBB, kFinRR) also publish the
+// scalars and flags to the host mirror, then the sequence number `seq`.
+__global__ void __launch_bounds__(kBlock)
+k_finalize(CgState st, int mode, int cnt, int seq) {
+    __shared__ double sh[kBlock / 64];
+    const int rhs = blockIdx.x;
+    if (mode != kFinBB && !st.active[rhs]) return;
+    const bool two = mode == kFinBetaFlex;
+    const double t1 = reduce_partials(st.partial + int64_t(rhs) * st.pstride, cnt, sh);
+    const double t2 = two ? reduce_partials(st.partial2 + int64_t(rhs) * st.pstride, cnt, sh) : 0.0;
+    if (threadIdx.x != 0) return;
+    double* v = st.sc + rhs * 8;
+    bool publish = false;
+    switch (mode) {
+        case kFinBB:
+            v[kBB] = t1;
+            v[kRR] = t1;
+            st.active[rhs] = (t1 > 0.0) ? 1 : 0;
+            publish = true;
+            break;
+        case kFinRho:
+            v[kRho] = t1;
+            break;
+        case kFinAlpha:
+            v[kPQ] = t1;
+            v[kAlpha] = v[kRho] / t1;
+            break;
+        case kFinRR:
+            v[kRR] = t1;
+            if (t1 <= v[kRtol2] * v[kBB]) st.active[rhs] = 0;
+            publish = true;
+            break;
+        case kFinBeta:
+            v[kBeta] = t1 / v[kRho];
+            v[kRho] = t1;
+            break;
+        case kFinBetaFlex:
+            // Polak-Ribiere: z.(r_new - r_old) / rho with r_new - r_old = -alpha q
+            v[kBeta] = -v[kAlpha] * t2 / v[kRho];
+            v[kZQ] = t2;
+            v[kRho] = t1;
+            break;
+    }
+    if (publish) {
+        for (int i = 0; i < 8; ++i) st.hsc[rhs * 8 + i] = v[i];
+        st.hact[rhs] = st.active[rhs];
+        __threadfence_system();
+        __hip_atomic_store(&st.hseq[rhs], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+}
+
 template <typename T, bool DOT, int KC>
 __global__ void __launch_bounds__(kBlock)
 k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, int nkc,
-        double* __restrict__ partial, int pstride, const int* __restrict__ active) {
+        CgState st, const int* __restrict__ active) {
     __shared__ double sh[kBlock / 64];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % batch, rest = lb / batch;
@@ -419,8 +516,9 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
         }
     }
     if (DOT) {
+        // p . q over the right-hand side's blocks, then alpha = rho / p.q
         const double s = block_sum(acc, sh);
-        if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + rest] = s;
+        store_partial(st, rhs, rest, s, 0.0, false);
     }
 }
 
@@ -649,22 +747,14 @@ k_convert(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
 
 // ---------------------------------------------------------------------------
 // Krylov (float64) kernels. Reductions are deterministic: a fixed grid of
-// `nblk` blocks per right-hand side writes one partial each, and one block
-// per right-hand side adds the partials in a fixed order.
+// blocks per right-hand side writes one partial sum each, and one block per
+// right-hand side adds the partials in a fixed order and derives the CG
+// scalar, so repeated runs give identical bits.
 //
-// Per right-hand-side scalars sc[rhs*8 + ...]:
-enum { kBB = 0, kRho = 1, kPQ = 2, kAlpha = 3, kRR = 4, kBeta = 5, kZQ = 6, kRtol2 = 7 };
-
-__device__ __forceinline__ void grid_range(int64_t n, int nblk, int blk, int64_t& i0, int64_t& i1) {
-    const int64_t per = (n + nblk - 1) / nblk;
-    i0 = min(n, int64_t(blk) * per);
-    i1 = min(n, i0 + per);
-}
-
 // x = 0, r = b, r32 = float(b); partial ||b||^2.
 __global__ void __launch_bounds__(kBlock)
 k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
-          float* __restrict__ r32, int64_t n, int nblk, double* __restrict__ partial, int pstride) {
+          float* __restrict__ r32, int64_t n, int nblk, CgState st) {
     __shared__ double sh[kBlock / 64];
     const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
     int64_t i0, i1;
@@ -680,19 +770,18 @@ k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restri
         acc += v * v;
     }
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + blk] = s;
+    store_partial(st, rhs, blk, s, 0.0, false);
 }
 
 // x += alpha p; r -= alpha q; r32 = float(r); partial ||r||^2.
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
             const double* __restrict__ p, const double* __restrict__ q, int64_t n, int nblk,
-            const double* __restrict__ sc, const int* __restrict__ active,
-            double* __restrict__ partial, int pstride) {
+            CgState st) {
     __shared__ double sh[kBlock / 64];
     const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
-    if (!active[rhs]) return;
-    const double alpha = sc[rhs * 8 + kAlpha];
+    if (!st.active[rhs]) return;
+    const double alpha = st.sc[rhs * 8 + kAlpha];
     int64_t i0, i1;
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
@@ -706,18 +795,17 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ 
         acc += v * v;
     }
     const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + blk] = s;
+    store_partial(st, rhs, blk, s, 0.0, false);
 }
 
 // partial r . z (and z . q for the flexible beta).
 template <typename Z>
 __global__ void __launch_bounds__(kBlock)
 k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __restrict__ q,
-         int64_t n, int nblk, const int* __restrict__ active, double* __restrict__ partial,
-         double* __restrict__ partial2, int pstride) {
+         int64_t n, int nblk, CgState st) {
     __shared__ double sh[kBlock / 64];
     const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
-    if (active && !active[rhs]) return;
+    if (!st.active[rhs]) return;
     int64_t i0, i1;
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
@@ -729,12 +817,12 @@ k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __
         if (q) a2 += zv * q[off + i];
     }
     const double s1 = block_sum(a1, sh);
-    if (threadIdx.x == 0) partial[int64_t(rhs) * pstride + blk] = s1;
+    double s2 = 0.0;
     if (q) {
         __syncthreads();
-        const double s2 = block_sum(a2, sh);
-        if (threadIdx.x == 0) partial2[int64_t(rhs) * pstride + blk] = s2;
+        s2 = block_sum(a2, sh);
     }
+    store_partial(st, rhs, blk, s1, s2, q != nullptr);
 }
 
 // p = z + beta p (init: p = z).
@@ -752,63 +840,6 @@ k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const double zv = double(z[off + i]);
         p[off + i] = init ? zv : zv + beta * p[off + i];
-    }
-}
-
-// One block per right-hand side: add `cnt` partials in a fixed order.
-__device__ __forceinline__ double reduce_partials(const double* __restrict__ part, int cnt,
-                                                  double* sh) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < cnt; i += kBlock) acc += part[i];
-    const double s = block_sum(acc, sh);
-    __syncthreads();
-    if (threadIdx.x == 0) sh[0] = s;
-    __syncthreads();
-    return sh[0];
-}
-
-enum FinalizeMode { kFinBB = 0, kFinRho = 1, kFinAlpha = 2, kFinRR = 3, kFinBeta = 4, kFinBetaFlex = 5 };
-
-__global__ void __launch_bounds__(kBlock)
-k_finalize(int mode, int cnt, const double* __restrict__ partial,
-           const double* __restrict__ partial2, int pstride, double* __restrict__ sc,
-           int* __restrict__ active) {
-    __shared__ double sh[kBlock / 64];
-    const int rhs = blockIdx.x;
-    const bool act = active[rhs] != 0;
-    if (mode != kFinBB && !act) return;
-    const double s = reduce_partials(partial + int64_t(rhs) * pstride, cnt, sh);
-    double s2 = 0.0;
-    if (mode == kFinBetaFlex) s2 = reduce_partials(partial2 + int64_t(rhs) * pstride, cnt, sh);
-    if (threadIdx.x != 0) return;
-    double* v = sc + rhs * 8;
-    switch (mode) {
-        case kFinBB:
-            v[kBB] = s;
-            v[kRR] = s;
-            active[rhs] = (s > 0.0) ? 1 : 0;
-            break;
-        case kFinRho:
-            v[kRho] = s;
-            break;
-        case kFinAlpha:
-            v[kPQ] = s;
-            v[kAlpha] = v[kRho] / s;
-            break;
-        case kFinRR:
-            v[kRR] = s;
-            if (s <= v[kRtol2] * v[kBB]) active[rhs] = 0;
-            break;
-        case kFinBeta:
-            v[kBeta] = s / v[kRho];
-            v[kRho] = s;
-            break;
-        case kFinBetaFlex:
-            // Polak-Ribiere: z.(r_new - r_old) / rho with r_new - r_old = -alpha q
-            v[kBeta] = -v[kAlpha] * s2 / v[kRho];
-            v[kZQ] = s2;
-            v[kRho] = s;
-            break;
     }
 }
 
