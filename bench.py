@@ -133,6 +133,44 @@ def cpu_baseline(w, kh, kv, delta, b, iters):
     }
 
 
+def batch_leg(Operator, torch, dev, steps=2, warmup=1):
+    """Largest single-GPU case: C384 x 70, batch of 4 right-hand sides sharing one
+    operator, float32 7-level V-cycle in float64 CG to 1e-6; one step is a forward
+    solve of all four plus the adjoint solve of all four and the face gradients."""
+    w = workloads.C384x70
+    kh, kv, delta = workloads.workload_coefficients(w)
+    b = torch.from_numpy(workloads.rhs(w.N, w.nz, w.batch)).to(dev)
+    g = torch.from_numpy(workloads.loss_weights(w.N, w.nz, w.batch)).to(dev)
+    op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", max_batch=w.batch,
+                  device=dev)
+    del kh, kv, delta
+
+    def step():
+        x = op.solve(b, rtol=1e-6)
+        lam = op.solve(g, rtol=1e-6)
+        op.face_grad(lam.x, x.x)
+        return x, lam
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        x, lam = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / steps * 1e3
+    true = [float(torch.linalg.norm(b[i] - op.apply(x.x[i])) / torch.linalg.norm(b[i]))
+            for i in range(w.batch)]
+    return {
+        "workload": f"{w.name} x batch {w.batch} ({w.n} unknowns per right-hand side)",
+        "ms_per_fwd_adj_step": ms,
+        "solves_per_s": 2 * w.batch * 1e3 / ms,
+        "iters_fwd": x.iters, "iters_adj": lam.iters,
+        "true_relres_max": max(true),
+        "workspace_GB": op.workspace_bytes / 1e9,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +179,8 @@ def main():
     ap.add_argument("--workload", default="C192x70", choices=sorted(workloads.ALL))
     ap.add_argument("--rtol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch-leg", action="store_true",
+                    help="skip the C384x70 batch-of-4 forward+adjoint measurement")
     ap.add_argument("--cg", default="standard", choices=["standard", "flexible"])
     ap.add_argument("--probe", action="store_true",
                     help="for counter runs: a few solves plus a 1 GiB device copy of known "
@@ -326,6 +366,10 @@ def main():
         "setup_ms": setup_ms,
         "adjoint_step_ms": adj_ms,
     }
+    if not args.no_batch_leg and args.workload == "C192x70":
+        del op32, op64, kh_d, kv_d, dl_d
+        torch.cuda.empty_cache()
+        out["batch4_C384x70"] = batch_leg(Operator, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, kh, kv, delta, b_np, int(round(it64)))
     print(json.dumps(out), flush=True)

@@ -314,12 +314,23 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
     const int kchunk = small_level(h, l) ? 1 : kApplyChunk;
     const int nkc = (h->nz + kchunk - 1) / kchunk;
     const dim3 grid(ntile * nkc * batch);
-    if (x)
-        hipLaunchKernelGGL((k_resid_restrict<T, false>), grid, dim3(kBlock), 0, s, view<T>(h, l),
-                           c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+    // child pairs load as one vector when b and x are aligned to two elements
+    // (the level's own arrays always are: rows hold an even number of columns)
+    const uintptr_t al = 2 * sizeof(T);
+    const bool pair = reinterpret_cast<uintptr_t>(b) % al == 0 &&
+                      reinterpret_cast<uintptr_t>(x) % al == 0;
+    if (x && pair)
+        hipLaunchKernelGGL((k_resid_restrict<T, false, true>), grid, dim3(kBlock), 0, s,
+                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+    else if (x)
+        hipLaunchKernelGGL((k_resid_restrict<T, false, false>), grid, dim3(kBlock), 0, s,
+                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+    else if (pair)
+        hipLaunchKernelGGL((k_resid_restrict<T, true, true>), grid, dim3(kBlock), 0, s,
+                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
     else
-        hipLaunchKernelGGL((k_resid_restrict<T, true>), grid, dim3(kBlock), 0, s, view<T>(h, l),
-                           c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+        hipLaunchKernelGGL((k_resid_restrict<T, true, false>), grid, dim3(kBlock), 0, s,
+                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
 }
 
 template <typename T>

@@ -532,7 +532,33 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
 //   bc = sum b - sum delta x - sum_{8 outer faces} K (x_in - x_out)
 //        - sum over children of the vertical fluxes.
 // One thread per (coarse column, chunk of KC levels); ZEROX: x = 0, bc = R b.
-template <typename T, bool ZEROX>
+// Children (0,0),(1,0) and (0,1),(1,1) are adjacent pairs in memory (same
+// panel row, even first index); PAIR loads each pair with one vector load
+// (the host uses it when b and x are aligned to two elements).
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+    using type = float2;
+};
+template <>
+struct Vec2<double> {
+    using type = double2;
+};
+
+template <typename T, bool PAIR>
+__device__ __forceinline__ void load_pair(const T* __restrict__ p, int64_t i, T& a, T& c) {
+    if (PAIR) {
+        const typename Vec2<T>::type v = *reinterpret_cast<const typename Vec2<T>::type*>(p + i);
+        a = v.x;
+        c = v.y;
+    } else {
+        a = p[i];
+        c = p[i + 1];
+    }
+}
+
+template <typename T, bool ZEROX, bool PAIR>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
                  const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
@@ -555,8 +581,10 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
     if (ZEROX) {
         for (int k = k0; k < k1; ++k) {
             const int64_t row = int64_t(k) * ncol;
-            bc[int64_t(k) * ncol_c + C] =
-                ((b[row + ch[0]] + b[row + ch[1]]) + b[row + ch[2]]) + b[row + ch[3]];
+            T v0, v1, v2, v3;
+            load_pair<T, PAIR>(b, row + ch[0], v0, v1);
+            load_pair<T, PAIR>(b, row + ch[2], v2, v3);
+            bc[int64_t(k) * ncol_c + C] = ((v0 + v1) + v2) + v3;
         }
         return;
     }
@@ -574,24 +602,30 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
         out[6] = F.nbr[0 * ncol + c11]; fc[6] = c11;
         out[7] = F.nbr[2 * ncol + c11]; fc[7] = ncol + c11;
     }
-    T xdn[4], xo[4], kvdn[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        xdn[s] = k0 > 0 ? x[int64_t(k0 - 1) * ncol + ch[s]] : T(0);
-        kvdn[s] = k0 > 0 ? F.kv[int64_t(k0 - 1) * ncol + ch[s]] : T(0);
-        xo[s] = x[int64_t(k0) * ncol + ch[s]];
+    T xdn[4] = {T(0), T(0), T(0), T(0)}, xo[4], kvdn[4] = {T(0), T(0), T(0), T(0)};
+    if (k0 > 0) {
+        const int64_t rdn = int64_t(k0 - 1) * ncol;
+        load_pair<T, PAIR>(x, rdn + ch[0], xdn[0], xdn[1]);
+        load_pair<T, PAIR>(x, rdn + ch[2], xdn[2], xdn[3]);
+        load_pair<T, PAIR>(F.kv, rdn + ch[0], kvdn[0], kvdn[1]);
+        load_pair<T, PAIR>(F.kv, rdn + ch[2], kvdn[2], kvdn[3]);
     }
+    load_pair<T, PAIR>(x, int64_t(k0) * ncol + ch[0], xo[0], xo[1]);
+    load_pair<T, PAIR>(x, int64_t(k0) * ncol + ch[2], xo[2], xo[3]);
     for (int k = k0; k < k1; ++k) {
         const int64_t row = int64_t(k) * ncol;
         const T* kh = F.kh + 2 * row;
-        T xup[4], vb[4], vd[4], vkv[4], vxo[8], vk[8];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            xup[s] = (k + 1 < nz) ? x[row + ncol + ch[s]] : T(0);
-            vb[s] = b[row + ch[s]];
-            vd[s] = F.dl[row + ch[s]];
-            vkv[s] = F.kv[row + ch[s]];
+        T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8];
+        if (k + 1 < nz) {
+            load_pair<T, PAIR>(x, row + ncol + ch[0], xup[0], xup[1]);
+            load_pair<T, PAIR>(x, row + ncol + ch[2], xup[2], xup[3]);
         }
+        load_pair<T, PAIR>(b, row + ch[0], vb[0], vb[1]);
+        load_pair<T, PAIR>(b, row + ch[2], vb[2], vb[3]);
+        load_pair<T, PAIR>(F.dl, row + ch[0], vd[0], vd[1]);
+        load_pair<T, PAIR>(F.dl, row + ch[2], vd[2], vd[3]);
+        load_pair<T, PAIR>(F.kv, row + ch[0], vkv[0], vkv[1]);
+        load_pair<T, PAIR>(F.kv, row + ch[2], vkv[2], vkv[3]);
 #pragma unroll
         for (int f = 0; f < 8; ++f) {
             vxo[f] = x[row + out[f]];
