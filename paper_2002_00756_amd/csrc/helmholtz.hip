@@ -22,6 +22,7 @@ namespace {
 
 constexpr int kRedBlocks = 2048;  // partial sums per right-hand side for vector reductions
 constexpr int kApplyChunk = 4;   // vertical levels per thread in apply / residual kernels
+constexpr int kSmallSweepCols = 5000;  // levels below this use narrow sweep tiles
 
 template <typename T>
 struct LevelData {
@@ -256,38 +257,53 @@ LevelData<T>& data(helmholtz_s* h, int l) {
 // ---- sweep launch: compile-time bound on levels per thread ---------------
 inline int sweep_mid(int nz) { return nz / 2; }
 
-template <typename T, int JMAX, int MODE, int NT>
+template <typename T, int JMAX, int MODE, int TC>
 void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
                     int batch, const int* active, hipStream_t s) {
     const Level& v = h->lev[l];
-    using Tile = SweepTile<T, 32, NT>;
-    const int ntile = (v.ncol + Tile::TC - 1) / Tile::TC;
+    using Tile = SweepTile<T, TC, kBlock>;
+    const int ntile = (v.ncol + TC - 1) / TC;
     const int32_t* par = (l + 1 < h->L) ? v.parent : nullptr;
     const int ncol_c = (l + 1 < h->L) ? h->lev[l + 1].ncol : 0;
     const bool prof = (l == 0 && MODE == kPlain) && prof_begin(h, HELMHOLTZ_PROF_SWEEP_FINE, s);
-    hipLaunchKernelGGL((k_sweep<T, JMAX, MODE, Tile::TC, NT>), dim3(ntile * batch), dim3(NT),
+    hipLaunchKernelGGL((k_sweep<T, JMAX, MODE, TC, kBlock>), dim3(ntile * batch), dim3(kBlock),
                        Tile::lds_bytes(h->nz), s, view<T>(h, l), b, x, xc, par, ncol_c,
                        y, T(h->cfg.omega), batch, active, sweep_mid(h->nz));
     if (prof)  // b, x, kh[2], cc, mm read; x_new written
         prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE, 7.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
 }
 
-template <typename T, int MODE>
-void launch_sweep_m(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
-                    int batch, const int* active, hipStream_t s) {
-    constexpr int KG = kBlock / 32;
+// Large levels: 32-column tiles (8 level groups, several workgroups per CU).
+// Small levels cannot fill the GPU and are bound by the latency of a few
+// dependent steps per thread: 8-column tiles with 32 level groups let each
+// thread load its few levels in one batch.
+template <typename T, int MODE, int TC>
+void launch_sweep_tc(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
+                     int batch, const int* active, hipStream_t s) {
+    constexpr int KG = kBlock / TC;
     const int jn = (h->nz + KG - 1) / KG;
-#define HH_SWEEP_BUCKET(J)                                                        \
-    if (jn <= J) {                                                                \
-        launch_sweep_b<T, J, MODE, kBlock>(h, l, b, x, xc, y, batch, active, s);  \
-        return;                                                                   \
+#define HH_SWEEP_BUCKET(J)                                                    \
+    if (jn <= J) {                                                            \
+        launch_sweep_b<T, J, MODE, TC>(h, l, b, x, xc, y, batch, active, s);  \
+        return;                                                               \
     }
     HH_SWEEP_BUCKET(1)
     HH_SWEEP_BUCKET(2)
     HH_SWEEP_BUCKET(4)
-    HH_SWEEP_BUCKET(9)
-    HH_SWEEP_BUCKET(15)
+    if (TC == 32) {
+        HH_SWEEP_BUCKET(9)
+        HH_SWEEP_BUCKET(15)
+    }
 #undef HH_SWEEP_BUCKET
+}
+
+template <typename T, int MODE>
+void launch_sweep_m(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
+                    int batch, const int* active, hipStream_t s) {
+    if (h->lev[l].ncol < kSmallSweepCols)
+        launch_sweep_tc<T, MODE, 8>(h, l, b, x, xc, y, batch, active, s);
+    else
+        launch_sweep_tc<T, MODE, 32>(h, l, b, x, xc, y, batch, active, s);
 }
 
 // Levels too small to fill the GPU are bound by the latency of a few dependent

@@ -99,3 +99,17 @@ def test_mesh_tables_bit_exact(lib, N):
         assert np.array_equal(par, omesh.parent(N))
     else:
         assert par is None
+
+
+def test_bench_byte_model():
+    """The V-cycle byte model of the benchmark, counted by hand for 2/2 sweeps:
+    per level 4 (first sweep) + 7 + 6.25 (residual + restriction) + 7.25
+    (sweep with prolongation) + 7 = 31.5 words, coarsest 4 + 3 * 7 = 25."""
+    import bench
+    assert bench.vcycle_words(1, 2, 2, 4) == 25.0
+    assert bench.vcycle_words(2, 2, 2, 4) == 31.5 + 25.0 / 4
+    L6 = 31.5 * sum(4.0 ** -l for l in range(5)) + 25.0 / 4 ** 5
+    assert abs(bench.vcycle_words(6, 2, 2, 4) - L6) < 1e-12
+    # one CG iteration: apply+dot 48, update 52 (mixed) / 48, dot 12 / 16, p-update 20 / 24
+    assert bench.cg_bytes_per_unknown(0.0, True, False) == 48 + 52 + 12 + 20
+    assert bench.cg_bytes_per_unknown(0.0, False, False) == 48 + 48 + 16 + 24
