@@ -24,23 +24,27 @@ constexpr int kRedBlocks = 2048;  // partial sums per right-hand side for vector
 constexpr int kApplyChunk = 4;   // vertical levels per thread in apply / residual kernels
 constexpr int kSmallSweepCols = 5000;  // levels below this use narrow sweep tiles
 
+// Per-level arrays use the column-tile layout of the kernels (element (k, c)
+// at tile_base(c) + 32 k, columns padded to ncolp, nvp = nz * ncolp).
 template <typename T>
 struct LevelData {
-    T* kh = nullptr;  // [nz][2][ncol]
-    T* kv = nullptr;  // [nz][ncol]
-    T* dl = nullptr;  // [nz][ncol]
-    T* cc = nullptr;  // [nz][ncol]
-    T* mm = nullptr;  // [nz][ncol]
-    T* b = nullptr;   // [B][nz][ncol]   level >= 1 (and level 0 for float32)
-    T* x = nullptr;   // [B][nz][ncol]   level >= 1 (and level 0 for float32)
-    T* t = nullptr;   // [B][nz][ncol]   ping-pong partner of x
+    T* kh = nullptr;  // [2][nvp]  E faces, N faces
+    T* kv = nullptr;  // [nvp]
+    T* dl = nullptr;  // [nvp]
+    T* cc = nullptr;  // [nvp]
+    T* mm = nullptr;  // [nvp]
+    T* b = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
+    T* x = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
+    T* t = nullptr;   // [B][nvp]   ping-pong partner of x
 };
 
 struct Level {
     int N = 0;
     int ncol = 0;
+    int ncolp = 0;              // ncol rounded up to whole tiles
+    int nvp = 0;                // nz * ncolp
     int32_t* nbr = nullptr;     // [4][ncol]
-    int32_t* fface = nullptr;   // [2][ncol]
+    uint32_t* fface = nullptr;  // [2][ncol] offsets of the W and S faces in kh
     int32_t* parent = nullptr;  // [ncol] into level + 1 (not on the coarsest)
     int32_t* child = nullptr;   // [4][ncol] into level - 1 (not on the finest)
     LevelData<double> d;
@@ -77,9 +81,11 @@ bool config_ok(const helmholtz_config* c) {
 int shape_error(const helmholtz_config* c) {
     if (c->N % (1 << (c->nlevels - 1)) != 0) return HELMHOLTZ_ESHAPE;
     const int64_t ncol = 6 * int64_t(c->N) * c->N;
-    // tables and face indices are 32-bit; batch offsets are 64-bit
+    const int64_t ncolp = (ncol + kTile - 1) / kTile * kTile;
+    // tables and offsets inside one vector are 32-bit (face offsets into the
+    // two kh planes unsigned); batch offsets are 64-bit
     if (2 * ncol >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
-    if (int64_t(c->nz) * ncol >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
+    if (int64_t(c->nz) * ncolp >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
     return HELMHOLTZ_OK;
 }
 
@@ -88,13 +94,15 @@ int shape_error(const helmholtz_config* c) {
 struct helmholtz_s {
     helmholtz_config cfg{};
     int L = 0, nz = 0, B = 0;
-    int64_t n = 0;  // unknowns per right-hand side on the finest level
+    int64_t n = 0;    // unknowns per right-hand side on the finest level
+    int64_t nvp = 0;  // tiled length of a finest-level vector (n plus padding)
     std::vector<Level> lev;
     // Krylov vectors [B][n]
     double* r = nullptr;
     double* p = nullptr;
     double* q = nullptr;
     double* z = nullptr;  // float64 preconditioned residual (float64 V-cycle)
+    // r, p, q, z are tiled [B][nvp]; x and b of the ABI are [B][n]
     double* partial = nullptr;
     double* partial2 = nullptr;
     int pstride = 0;
@@ -126,9 +134,9 @@ void layout(helmholtz_s* h, Carver& cv) {
     for (int l = 0; l < h->L; ++l) {
         Level& v = h->lev[l];
         const size_t nc = size_t(v.ncol);
-        const size_t nv = size_t(nz) * nc;
+        const size_t nv = size_t(v.nvp);
         v.nbr = cv.take<int32_t>(4 * nc);
-        v.fface = cv.take<int32_t>(2 * nc);
+        v.fface = cv.take<uint32_t>(2 * nc);
         v.parent = (l + 1 < h->L) ? cv.take<int32_t>(nc) : nullptr;
         v.child = (l > 0) ? cv.take<int32_t>(4 * nc) : nullptr;
         v.d.kh = cv.take<double>(2 * nv);
@@ -151,14 +159,15 @@ void layout(helmholtz_s* h, Carver& cv) {
         v.f.x = cv.take<float>(size_t(B) * nv);
         v.f.t = cv.take<float>(size_t(B) * nv);
     }
-    const size_t nb = size_t(B) * size_t(h->n);
+    const size_t nb = size_t(B) * size_t(h->nvp);
     h->r = cv.take<double>(nb);
     h->p = cv.take<double>(nb);
     h->q = cv.take<double>(nb);
     h->z = cv.take<double>(nb);
     const int ntile0 = (h->lev[0].ncol + kBlock - 1) / kBlock;
     const int nkc0 = (nz + kApplyChunk - 1) / kApplyChunk;
-    h->pstride = std::max(kRedBlocks, ntile0 * nkc0);
+    const int ntile32 = h->lev[0].ncolp / kTile;
+    h->pstride = std::max(std::max(kRedBlocks, ntile0 * nkc0), ntile32);
     h->partial = cv.take<double>(size_t(B) * h->pstride);
     h->partial2 = cv.take<double>(size_t(B) * h->pstride);
     h->sc = cv.take<double>(size_t(B) * 8);
@@ -173,10 +182,14 @@ void init_shape(helmholtz_s* h, const helmholtz_config* cfg) {
     h->B = cfg->max_batch;
     h->lev.assign(h->L, Level{});
     for (int l = 0; l < h->L; ++l) {
-        h->lev[l].N = cfg->N >> l;
-        h->lev[l].ncol = 6 * h->lev[l].N * h->lev[l].N;
+        Level& v = h->lev[l];
+        v.N = cfg->N >> l;
+        v.ncol = 6 * v.N * v.N;
+        v.ncolp = (v.ncol + kTile - 1) / kTile * kTile;
+        v.nvp = cfg->nz * v.ncolp;
     }
     h->n = int64_t(cfg->nz) * h->lev[0].ncol;
+    h->nvp = h->lev[0].nvp;
 }
 
 inline int grid_for(int64_t n) {
@@ -245,7 +258,7 @@ LevelView<T> view(const helmholtz_s* h, int l) {
         if constexpr (std::is_same<T, double>::value) return v.d;
         else return v.f;
     }();
-    return LevelView<T>{v.ncol, h->nz, v.nbr, v.fface, d.kh, d.kv, d.dl, d.cc, d.mm};
+    return LevelView<T>{v.ncol, h->nz, v.nvp, v.nbr, v.fface, d.kh, d.kv, d.dl, d.cc, d.mm};
 }
 
 template <typename T>
@@ -264,10 +277,10 @@ void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T
     using Tile = SweepTile<T, TC, kBlock>;
     const int ntile = (v.ncol + TC - 1) / TC;
     const int32_t* par = (l + 1 < h->L) ? v.parent : nullptr;
-    const int ncol_c = (l + 1 < h->L) ? h->lev[l + 1].ncol : 0;
+    const int nvp_c = (l + 1 < h->L) ? h->lev[l + 1].nvp : 0;
     const bool prof = (l == 0 && MODE == kPlain) && prof_begin(h, HELMHOLTZ_PROF_SWEEP_FINE, s);
     hipLaunchKernelGGL((k_sweep<T, JMAX, MODE, TC, kBlock>), dim3(ntile * batch), dim3(kBlock),
-                       Tile::lds_bytes(h->nz), s, view<T>(h, l), b, x, xc, par, ncol_c,
+                       Tile::lds_bytes(h->nz), s, view<T>(h, l), b, x, xc, par, nvp_c,
                        y, T(h->cfg.omega), batch, active, sweep_mid(h->nz));
     if (prof)  // b, x, kh[2], cc, mm read; x_new written
         prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE, 7.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
@@ -331,22 +344,22 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
     const int nkc = (h->nz + kchunk - 1) / kchunk;
     const dim3 grid(ntile * nkc * batch);
     // child pairs load as one vector when b and x are aligned to two elements
-    // (the level's own arrays always are: rows hold an even number of columns)
+    // (the level's own arrays always are: tiles hold an even number of values)
     const uintptr_t al = 2 * sizeof(T);
     const bool pair = reinterpret_cast<uintptr_t>(b) % al == 0 &&
                       reinterpret_cast<uintptr_t>(x) % al == 0;
     if (x && pair)
         hipLaunchKernelGGL((k_resid_restrict<T, false, true>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
     else if (x)
         hipLaunchKernelGGL((k_resid_restrict<T, false, false>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
     else if (pair)
         hipLaunchKernelGGL((k_resid_restrict<T, true, true>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
     else
         hipLaunchKernelGGL((k_resid_restrict<T, true, false>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, b, x, bc, batch, kchunk, nkc, active);
+                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
 }
 
 template <typename T>
@@ -416,7 +429,7 @@ void vcycle_level(helmholtz_s* h, int l, const T* b, T* out, int batch, const in
         const Level& v = h->lev[l];
         const int64_t total = int64_t(batch) * h->nz * v.ncol;
         hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(total)), dim3(kBlock), 0, s, v.ncol,
-                           h->nz, h->lev[l + 1].ncol, v.parent, prev, c.x, dst, total);
+                           h->nz, v.nvp, h->lev[l + 1].nvp, v.parent, prev, c.x, dst, total);
         return;
     }
     for (int i = 0; i < cfg.n_post; ++i, ++j) {
@@ -439,18 +452,25 @@ void convert(const S* src, D* dst, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL((k_convert<S, D>), dim3(grid_for(n)), dim3(kBlock), 0, s, src, dst, n);
 }
 
-// z = M r on the finest level in the handle's precision; r32/z32 are the
-// float32 level-0 buffers (already holding float(r) when called from solve).
-int precondition(helmholtz_s* h, const double* r, double* z, int batch, bool r32_ready,
-                 const int* active, hipStream_t s) {
+// Finest-level vector between the ABI layout and the tiled layout, with a cast.
+template <typename S, typename D, bool TO_TILED>
+void retile(const helmholtz_s* h, const S* src, D* dst, int batch, hipStream_t s) {
+    const Level& v = h->lev[0];
+    hipLaunchKernelGGL((k_retile<S, D, TO_TILED>), dim3(v.ncolp / kTile * batch), dim3(kBlock), 0,
+                       s, src, dst, v.ncol, h->nz, v.nvp);
+}
+
+// z = M r on the finest level in the handle's precision (tiled vectors). The
+// float32 V-cycle reads r32 (the level-0 float32 right-hand side, which the
+// Krylov kernels keep equal to float(r)) and leaves z32 in the level-0 float32
+// solution buffer; r and z are then not touched.
+int precondition(helmholtz_s* h, const double* r, double* z, int batch, const int* active,
+                 hipStream_t s) {
     if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
         vcycle_level<double>(h, 0, r, z, batch, active, s);
     } else {
         LevelData<float>& f = h->lev[0].f;
-        const int64_t n = int64_t(batch) * h->n;
-        if (!r32_ready) convert<double, float>(r, f.b, n, s);
         vcycle_level<float>(h, 0, f.b, f.x, batch, active, s);
-        if (z) convert<float, double>(f.x, z, n, s);
     }
     return last_error();
 }
@@ -534,6 +554,8 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
     const size_t need = helmholtz_workspace_bytes(cfg);
     if (workspace_bytes < need) return HELMHOLTZ_EWORKSPACE;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream_);
+    // padding columns of the tiled arrays must read as zero
+    if (hipMemsetAsync(workspace, 0, need, s) != hipSuccess) return HELMHOLTZ_EHIP;
 
     helmholtz_s* h = new (std::nothrow) helmholtz_s;
     if (!h) return HELMHOLTZ_EINVAL;
@@ -570,10 +592,17 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
         if (hipMemcpyAsync(v.nbr, tab.data(), 4 * nc * sizeof(int32_t), hipMemcpyHostToDevice, s) !=
             hipSuccess)
             return fail(HELMHOLTZ_EHIP);
-        std::vector<int32_t> ff(2 * nc);
-        std::copy(ft.begin() + nc, ft.begin() + 2 * nc, ff.begin());       // W
-        std::copy(ft.begin() + 3 * nc, ft.begin() + 4 * nc, ff.begin() + nc);  // S
-        if (hipMemcpyAsync(v.fface, ff.data(), 2 * nc * sizeof(int32_t), hipMemcpyHostToDevice,
+        // W and S faces: stored face slot * ncol + owner -> offset in the tiled kh
+        std::vector<uint32_t> ff(2 * nc);
+        for (size_t c = 0; c < nc; ++c) {
+            for (int w = 0; w < 2; ++w) {
+                const int32_t f = ft[(w == 0 ? 1 : 3) * nc + c];
+                const int slot = f >= v.ncol ? 1 : 0, owner = f - slot * v.ncol;
+                ff[w * nc + c] = uint32_t(slot) * uint32_t(v.nvp) +
+                                 uint32_t((owner / kTile) * kTile * nz + owner % kTile);
+            }
+        }
+        if (hipMemcpyAsync(v.fface, ff.data(), 2 * nc * sizeof(uint32_t), hipMemcpyHostToDevice,
                            s) != hipSuccess)
             return fail(HELMHOLTZ_EHIP);
         if (v.parent) {
@@ -599,23 +628,22 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
     {
         Level& v = h->lev[0];
         const int64_t nv = int64_t(nz) * v.ncol;
-        hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(nv)), dim3(kBlock), 0, s, v.ncol, nz, kh,
-                           kv, delta, v.d.kh, v.d.kv, v.d.dl, h->flags);
+        hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(nv)), dim3(kBlock), 0, s, v.ncol, nz,
+                           v.nvp, kh, kv, delta, v.d.kh, v.d.kv, v.d.dl, h->flags);
     }
     for (int l = 1; l < h->L; ++l) {
         Level& f = h->lev[l - 1];
         Level& c = h->lev[l];
         const int64_t nv = int64_t(nz) * c.ncol;
-        hipLaunchKernelGGL(k_coarsen, dim3(grid_for(nv)), dim3(kBlock), 0, s, f.ncol, c.ncol, nz,
-                           c.child, f.d.kh, f.d.kv, f.d.dl, c.d.kh, c.d.kv, c.d.dl);
+        hipLaunchKernelGGL(k_coarsen, dim3(grid_for(nv)), dim3(kBlock), 0, s, c.ncol, nz, f.nvp,
+                           c.nvp, c.child, f.d.kh, f.d.kv, f.d.dl, c.d.kh, c.d.kv, c.d.dl);
     }
     for (int l = 0; l < h->L; ++l) {
         Level& v = h->lev[l];
         hipLaunchKernelGGL(k_factor, dim3((v.ncol + kBlock - 1) / kBlock), dim3(kBlock), 0, s,
                            view<double>(h, l), sweep_mid(nz), v.d.cc, v.d.mm);
-        // float32 copies, rounded once from float64 (kh, kv, dl, cc, mm are
-        // contiguous in both precisions)
-        const int64_t nv = int64_t(nz) * v.ncol;
+        // float32 copies, rounded once from float64 (padding included)
+        const int64_t nv = v.nvp;
         convert<double, float>(v.d.kh, v.f.kh, 2 * nv, s);
         convert<double, float>(v.d.kv, v.f.kv, nv, s);
         convert<double, float>(v.d.dl, v.f.dl, nv, s);
@@ -665,7 +693,10 @@ int helmholtz_apply(helmholtz_t h, const double* x, double* y, int32_t batch,
                     helmholtz_stream_t stream) {
     if (int e = check_batch(h, batch)) return e;
     if (!x || !y) return HELMHOLTZ_EINVAL;
-    launch_apply<double>(h, 0, x, y, batch, false, nullptr, reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    retile<double, double, true>(h, x, h->p, batch, s);
+    launch_apply<double>(h, 0, h->p, h->q, batch, false, nullptr, s);
+    retile<double, double, false>(h, h->q, y, batch, s);
     return last_error();
 }
 
@@ -673,14 +704,29 @@ int helmholtz_vcycle(helmholtz_t h, const double* b, double* x, int32_t batch,
                      helmholtz_stream_t stream) {
     if (int e = check_batch(h, batch)) return e;
     if (!b || !x) return HELMHOLTZ_EINVAL;
-    return precondition(h, b, x, batch, false, nullptr, reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
+        retile<double, double, true>(h, b, h->r, batch, s);
+        if (int e = precondition(h, h->r, h->z, batch, nullptr, s)) return e;
+        retile<double, double, false>(h, h->z, x, batch, s);
+    } else {
+        LevelData<float>& f = h->lev[0].f;
+        retile<double, float, true>(h, b, f.b, batch, s);
+        if (int e = precondition(h, nullptr, nullptr, batch, nullptr, s)) return e;
+        retile<float, double, false>(h, f.x, x, batch, s);
+    }
+    return last_error();
 }
 
 int helmholtz_vcycle_f32(helmholtz_t h, const float* b, float* x, int32_t batch,
                          helmholtz_stream_t stream) {
     if (int e = check_batch(h, batch)) return e;
     if (!b || !x) return HELMHOLTZ_EINVAL;
-    vcycle_level<float>(h, 0, b, x, batch, nullptr, reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    LevelData<float>& f = h->lev[0].f;
+    retile<float, float, true>(h, b, f.b, batch, s);
+    vcycle_level<float>(h, 0, f.b, f.x, batch, nullptr, s);
+    retile<float, float, false>(h, f.x, x, batch, s);
     return last_error();
 }
 
@@ -689,7 +735,10 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     if (int e = check_batch(h, batch)) return e;
     if (!b || !x || maxiter < 1 || !(rtol >= 0.0)) return HELMHOLTZ_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int64_t n = h->n;
+    const int64_t n = h->nvp;  // tiled vector length (elementwise kernels)
+    const Level& v0 = h->lev[0];
+    const int ntile32 = v0.ncolp / kTile;
+    const dim3 tgrid(ntile32 * batch);
     const bool mixed = h->cfg.mg_precision == HELMHOLTZ_FP32;
     const bool flex = h->cfg.cg_variant == HELMHOLTZ_CG_FLEXIBLE;
     float* r32 = mixed ? h->lev[0].f.b : nullptr;
@@ -706,8 +755,8 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     HH_CHECK(hipMemcpyAsync(h->sc, h->hsc, size_t(batch) * 8 * sizeof(double),
                             hipMemcpyHostToDevice, s));
     // x = 0, r = b, ||b||^2
-    hipLaunchKernelGGL(k_cg_init, red, blk, 0, s, b, x, h->r, r32, n, kRedBlocks, st);
-    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinBB), kRedBlocks, 0);
+    hipLaunchKernelGGL(k_cg_init, tgrid, blk, 0, s, b, x, h->r, r32, v0.ncol, h->nz, v0.nvp, st);
+    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinBB), ntile32, 0);
     if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
     std::vector<int> need(batch, 1);
     if (int e = wait_published(h, s, need, 0)) return e;
@@ -731,7 +780,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     if (!any) return finish(HELMHOLTZ_OK);
 
     // z = M r, rho = r.z, p = z
-    if (int e = precondition(h, h->r, mixed ? nullptr : h->z, batch, true, h->active, s)) return e;
+    if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
     if (mixed)
         hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, nullptr, n, kRedBlocks,
                            st);
@@ -757,9 +806,9 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
                            0);
         // x += alpha p, r -= alpha q, ||r||^2 and the convergence flags, published
-        hipLaunchKernelGGL(k_cg_update, red, blk, 0, s, x, h->r, r32, h->p, h->q, n, kRedBlocks,
-                           st);
-        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinRR), kRedBlocks, iter);
+        hipLaunchKernelGGL(k_cg_update, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q, v0.ncol,
+                           h->nz, v0.nvp, st);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinRR), ntile32, iter);
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
         if (int e = wait_published(h, s, was_active, iter)) return e;
         bool still = false;
@@ -777,8 +826,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
             break;
         }
         // z = M r, beta, p = z + beta p
-        if (int e = precondition(h, h->r, mixed ? nullptr : h->z, batch, true, h->active, s))
-            return e;
+        if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
         const double* qarg = flex ? h->q : nullptr;
         if (mixed)
             hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, qarg, n, kRedBlocks,

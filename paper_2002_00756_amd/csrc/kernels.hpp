@@ -1,16 +1,29 @@
 // Device kernels of the Helmholtz multigrid path (gfx950, wave64).
 //
-// Data layout in HBM, per multigrid level with ncol columns and nz levels:
-//   vectors        [batch][nz][ncol]   column index fastest: lane = column gives
-//                                      one coalesced row per vertical level
-//   kh             [nz][2][ncol]       per level k: E faces, then N faces
-//   kv             [nz][ncol]          face k|k+1; row nz-1 is zero (no flux
+// Data layout in HBM, per multigrid level with ncol columns and nz levels.
+// Columns are grouped into tiles of kTile = 32 consecutive columns, and every
+// per-level array stores one tile after the other, each tile holding its nz
+// levels as rows of 32 values:
+//     element (k, c) sits at tile_base(c) + 32 k,
+//     tile_base(c) = (c / 32) * 32 nz + c % 32.
+// For storage ncol is rounded up to ncolp, a multiple of 32; the padding
+// columns hold zeros (the workspace is cleared at set-up and no kernel writes
+// them), so reductions may run over the padded length. nvp = nz * ncolp.
+//   vectors        [batch][nvp]        tiled as above
+//   kh             [2][nvp]            E-face plane, then N-face plane
+//   kv             [nvp]               face k|k+1; row nz-1 is zero (no flux
 //                                      through the top), so loads need no guard
-//   dl (delta)     [nz][ncol]
-//   cc, mm         [nz][ncol]          factors of the column operator (below)
+//   dl (delta)     [nvp]
+//   cc, mm         [nvp]               factors of the column operator (below)
 //   nbr            [4][ncol]           E, W, N, S neighbour column
-//   fface          [2][ncol]           stored face index (slot*ncol + owner) of
-//                                      the W and S faces; E and N are c, ncol+c
+//   fface          [2][ncol]           offset in kh of the W and S face at
+//                                      level 0 (plane * nvp + tile_base(owner));
+//                                      the E and N faces are at tile_base(c)
+//                                      and nvp + tile_base(c)
+// A workgroup that owns a tile reads one contiguous block of every array and
+// a wave reads two adjacent rows of one tile. Vectors passed through the C ABI
+// keep the natural [batch][nz][ncol] layout; the kernels that take them in or
+// hand them out convert on the fly.
 //
 // Column factorisation. The smoother solves with the column operator Hz (all
 // couplings inside a column plus the full diagonal of H; Section 3.5, Eq.
@@ -45,11 +58,18 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
     return xcd * q + (xcd < r ? xcd : r) + slot;
 }
 
+constexpr int kTile = 32;
+
+// Offset of element (0, c) of a tiled array; element (k, c) is 32 k further.
+__device__ __forceinline__ int tile_base(int c, int nz) {
+    return (c >> 5) * (kTile * nz) + (c & (kTile - 1));
+}
+
 template <typename T>
 struct LevelView {
-    int ncol, nz;
+    int ncol, nz, nvp;
     const int32_t* __restrict__ nbr;
-    const int32_t* __restrict__ fface;
+    const uint32_t* __restrict__ fface;
     const T* __restrict__ kh;
     const T* __restrict__ kv;
     const T* __restrict__ dl;
@@ -91,6 +111,9 @@ enum SweepMode { kZero = 0, kPlain = 1, kProlong = 2, kProlongZero = 3 };
 // Two lanes per column (tid < ncol: rows above mid, top-down; BOT <= tid <
 // BOT + ncol: rows below mid, bottom-up) walk the column, SEQ levels per LDS
 // round trip; row mid combines both eliminations. E1, E2 hold ncol values.
+// The SEQ reads of a round trip use row indices clamped into the walker's
+// own half of the column, so they are unconditional and issue together; the
+// range test only guards the arithmetic and the stores.
 template <typename T, int JMAX>
 __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T (&mo)[JMAX],
                                              int tid, int lc, int kg, int KG, int BOT, int mid,
@@ -103,9 +126,9 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             T rr[SEQ], cf[SEQ];
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
-                const int k = k0 + i;
-                rr[i] = k < mid ? R[k * S + tid] : T(0);
-                cf[i] = k < mid ? Cf[k * S + tid] : T(0);
+                const int k = min(k0 + i, mid - 1);
+                rr[i] = R[k * S + tid];
+                cf[i] = Cf[k * S + tid];
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
@@ -127,9 +150,9 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             T rr[SEQ], cf[SEQ];
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
-                const int k = k0 - i;
-                rr[i] = k > mid ? R[k * S + l2] : T(0);
-                cf[i] = k > mid ? Cf[k * S + l2] : T(0);
+                const int k = max(k0 - i, mid + 1);
+                rr[i] = R[k * S + l2];
+                cf[i] = Cf[k * S + l2];
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
@@ -168,14 +191,16 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             T rr[SEQ], cf[SEQ];
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
-                const int k = k0 - i;
-                rr[i] = k >= 0 ? R[k * S + tid] : T(0);
-                cf[i] = k >= 0 ? Cf[k * S + tid] : T(0);
+                const int k = max(k0 - i, 0);
+                rr[i] = R[k * S + tid];
+                cf[i] = Cf[k * S + tid];
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
-                z = rr[i] + cf[i] * z;
-                rr[i] = z;
+                if (k0 - i >= 0) {
+                    z = rr[i] + cf[i] * z;
+                    rr[i] = z;
+                }
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i)
@@ -188,14 +213,16 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
             T rr[SEQ], cf[SEQ];
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
-                const int k = k0 + i;
-                rr[i] = k < nz ? R[k * S + l2] : T(0);
-                cf[i] = k < nz ? Cf[k * S + l2] : T(0);
+                const int k = min(k0 + i, nz - 1);
+                rr[i] = R[k * S + l2];
+                cf[i] = Cf[k * S + l2];
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i) {
-                z = rr[i] + cf[i] * z;
-                rr[i] = z;
+                if (k0 + i < nz) {
+                    z = rr[i] + cf[i] * z;
+                    rr[i] = z;
+                }
             }
 #pragma unroll
             for (int i = 0; i < SEQ; ++i)
@@ -217,11 +244,12 @@ template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = k
           int CH_ = 0>
 __global__ void __launch_bounds__(NT)
 k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
-        const T* __restrict__ xc, const int32_t* __restrict__ parent, int ncol_c,
+        const T* __restrict__ xc, const int32_t* __restrict__ parent, int nvp_c,
         T* __restrict__ y, T omega, int batch, const int* __restrict__ active, int mid) {
     constexpr int TC = TC_, KG = NT / TC;
     constexpr int BOT = (TC + 63) / 64 * 64;  // first lane of the bottom elimination (own wave)
     static_assert(BOT + TC <= NT, "two elimination lane groups must fit the workgroup");
+    static_assert(kTile % TC == 0, "a sweep tile lies inside one storage tile");
     constexpr bool kHasX = MODE == kPlain || MODE == kProlong;
     constexpr bool kHasP = MODE == kProlong || MODE == kProlongZero;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -238,29 +266,34 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     const int lc = tid % TC, kg = tid / TC;
     const int c = tile * TC + lc;
     const bool valid = c < ncol;
-    const int64_t nv = int64_t(nz) * ncol;
+    const int64_t nv = L.nvp;
     b += rhs * nv;
     y += rhs * nv;
     if (kHasX) x += rhs * nv;
-    if (kHasP) xc += rhs * int64_t(nz) * ncol_c;
+    if (kHasP) xc += rhs * int64_t(nvp_c);
+    const T* khN = L.kh + nv;
+    const int ob = tile_base(c, nz);
 
     // ---- phase 1: right-hand side and factors into LDS --------------------
-    int nb[4] = {0, 0, 0, 0}, pn[5] = {0, 0, 0, 0, 0}, fW = 0, fS = 0;
+    // nb: tiled offsets of the neighbours (and of the parents on the coarse
+    // level, pn); fW, fS: offsets of the W and S faces in kh.
+    int nb[4] = {0, 0, 0, 0}, pn[5] = {0, 0, 0, 0, 0};
+    uint32_t fW = 0, fS = 0;
     if (MODE != kZero && valid) {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) nb[d] = L.nbr[d * ncol + c];
+        for (int d = 0; d < 4; ++d) {
+            const int cn = L.nbr[d * ncol + c];
+            nb[d] = tile_base(cn, nz);
+            if (kHasP) pn[d] = tile_base(parent[cn], nz);
+        }
         fW = L.fface[c];
         fS = L.fface[ncol + c];
-        if (kHasP) {
-#pragma unroll
-            for (int d = 0; d < 4; ++d) pn[d] = parent[nb[d]];
-            pn[4] = parent[c];
-        }
+        if (kHasP) pn[4] = tile_base(parent[c], nz);
     }
-    auto xv = [&](int k, int col, int pcol) -> T {
+    auto xv = [&](int k, int off, int poff) -> T {
         T v = T(0);
-        if (kHasX) v = x[int64_t(k) * ncol + col];
-        if (kHasP) v += xc[int64_t(k) * ncol_c + pcol];
+        if (kHasX) v = x[off + kTile * k];
+        if (kHasP) v += xc[poff + kTile * k];
         return v;
     };
     // Loads of CH levels are issued together before any is used, so each
@@ -280,19 +313,18 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
 #pragma unroll
             for (int d = 0; d < 4; ++d) vk[jj][d] = T(0);
             if (j < JMAX && k < nz && valid) {
-                const int64_t row = int64_t(k) * ncol;
-                vb[jj] = b[row + c];
-                vc[jj] = L.cc[row + c];
-                vm[jj] = L.mm[row + c];
+                const int o = ob + kTile * k;
+                vb[jj] = b[o];
+                vc[jj] = L.cc[o];
+                vm[jj] = L.mm[o];
                 if (MODE != kZero) {
-                    const T* kh = L.kh + 2 * row;
-                    vk[jj][0] = kh[c];
-                    vk[jj][1] = kh[fW];
-                    vk[jj][2] = kh[ncol + c];
-                    vk[jj][3] = kh[fS];
+                    vk[jj][0] = L.kh[o];
+                    vk[jj][1] = L.kh[fW + uint32_t(kTile * k)];
+                    vk[jj][2] = khN[o];
+                    vk[jj][3] = L.kh[fS + uint32_t(kTile * k)];
 #pragma unroll
                     for (int d = 0; d < 4; ++d) vx[jj][d] = xv(k, nb[d], pn[d]);
-                    vx[jj][4] = xv(k, c, pn[4]);
+                    vx[jj][4] = xv(k, ob, pn[4]);
                 }
             }
         }
@@ -324,7 +356,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         const int k = kg + j * KG;
         if (k < nz) {
             const T z = R[k * TC + lc];
-            y[int64_t(k) * ncol + c] = (MODE == kZero) ? om * z : om1 * xo[j] + om * z;
+            y[ob + kTile * k] = (MODE == kZero) ? om * z : om1 * xo[j] + om * z;
         }
     }
 }
@@ -460,27 +492,29 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
     const int ncol = L.ncol, nz = L.nz;
     const int c = tile * kBlock + threadIdx.x;
     const bool valid = c < ncol;
-    const int64_t nv = int64_t(nz) * ncol;
+    const int64_t nv = L.nvp;
     x += rhs * nv;
     y += rhs * nv;
+    const T* khN = L.kh + nv;
     double acc = 0.0;
     if (valid) {
         int nb[4];
 #pragma unroll
-        for (int d = 0; d < 4; ++d) nb[d] = L.nbr[d * ncol + c];
-        const int fW = L.fface[c], fS = L.fface[ncol + c];
+        for (int d = 0; d < 4; ++d) nb[d] = tile_base(L.nbr[d * ncol + c], nz);
+        const uint32_t fW = L.fface[c], fS = L.fface[ncol + c];
+        const int ob = tile_base(c, nz);
         const int k0 = kc * KC;
         // all loads of the chunk are issued before any is used
         T xc[KC + 2], kvv[KC + 1], dl[KC], xn[KC][4], kh[KC][4];
 #pragma unroll
         for (int j = 0; j < KC + 2; ++j) {
             const int k = k0 - 1 + j;
-            xc[j] = (k >= 0 && k < nz) ? x[int64_t(k) * ncol + c] : T(0);
+            xc[j] = (k >= 0 && k < nz) ? x[ob + kTile * k] : T(0);
         }
 #pragma unroll
         for (int j = 0; j < KC + 1; ++j) {
             const int k = k0 - 1 + j;
-            kvv[j] = (k >= 0 && k < nz) ? L.kv[int64_t(k) * ncol + c] : T(0);
+            kvv[j] = (k >= 0 && k < nz) ? L.kv[ob + kTile * k] : T(0);
         }
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
@@ -489,15 +523,14 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
 #pragma unroll
             for (int d = 0; d < 4; ++d) xn[j][d] = kh[j][d] = T(0);
             if (k < nz) {
-                const int64_t row = int64_t(k) * ncol;
-                const T* khr = L.kh + 2 * row;
-                dl[j] = L.dl[row + c];
+                const int o = ob + kTile * k;
+                dl[j] = L.dl[o];
 #pragma unroll
-                for (int d = 0; d < 4; ++d) xn[j][d] = x[row + nb[d]];
-                kh[j][0] = khr[c];
-                kh[j][1] = khr[fW];
-                kh[j][2] = khr[ncol + c];
-                kh[j][3] = khr[fS];
+                for (int d = 0; d < 4; ++d) xn[j][d] = x[nb[d] + kTile * k];
+                kh[j][0] = L.kh[o];
+                kh[j][1] = L.kh[fW + uint32_t(kTile * k)];
+                kh[j][2] = khN[o];
+                kh[j][3] = L.kh[fS + uint32_t(kTile * k)];
             }
         }
 #pragma unroll
@@ -510,7 +543,7 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
                 for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
                 v += kvv[j + 1] * (xo - xc[j + 2]);
                 v += kvv[j] * (xo - xc[j]);
-                y[int64_t(k) * ncol + c] = v;
+                y[ob + kTile * k] = v;
                 if (DOT) acc += double(xo) * double(v);
             }
         }
@@ -533,8 +566,8 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
 //        - sum over children of the vertical fluxes.
 // One thread per (coarse column, chunk of KC levels); ZEROX: x = 0, bc = R b.
 // Children (0,0),(1,0) and (0,1),(1,1) are adjacent pairs in memory (same
-// panel row, even first index); PAIR loads each pair with one vector load
-// (the host uses it when b and x are aligned to two elements).
+// panel row, even first index, so the same tile); PAIR loads each pair with
+// one vector load (the host uses it when b and x are aligned to two elements).
 template <typename T>
 struct Vec2;
 template <>
@@ -560,7 +593,7 @@ __device__ __forceinline__ void load_pair(const T* __restrict__ p, int64_t i, T&
 
 template <typename T, bool ZEROX, bool PAIR>
 __global__ void __launch_bounds__(kBlock)
-k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
+k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
                  const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
                  int batch, int kchunk, int nkc, const int* __restrict__ active) {
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
@@ -570,66 +603,74 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
     const int C = tile * kBlock + threadIdx.x;
     if (C >= ncol_c) return;
     const int ncol = F.ncol, nz = F.nz;
-    const int64_t nv = int64_t(nz) * ncol;
+    const int64_t nv = F.nvp;
     b += rhs * nv;
     if (!ZEROX) x += rhs * nv;
-    bc += rhs * int64_t(nz) * ncol_c;
-    int ch[4];
+    bc += rhs * int64_t(nvp_c) + tile_base(C, nz);
+    // children (0,0), (1,0) share a tile and are adjacent, as are (0,1), (1,1)
+    int ch[4], cb[4];
 #pragma unroll
-    for (int s = 0; s < 4; ++s) ch[s] = child[s * ncol_c + C];
+    for (int s = 0; s < 4; ++s) {
+        ch[s] = child[s * ncol_c + C];
+        cb[s] = tile_base(ch[s], nz);
+    }
     const int k0 = kc * kchunk, k1 = min(nz, k0 + kchunk);
     if (ZEROX) {
         for (int k = k0; k < k1; ++k) {
-            const int64_t row = int64_t(k) * ncol;
+            const int r = kTile * k;
             T v0, v1, v2, v3;
-            load_pair<T, PAIR>(b, row + ch[0], v0, v1);
-            load_pair<T, PAIR>(b, row + ch[2], v2, v3);
-            bc[int64_t(k) * ncol_c + C] = ((v0 + v1) + v2) + v3;
+            load_pair<T, PAIR>(b, r + cb[0], v0, v1);
+            load_pair<T, PAIR>(b, r + cb[2], v2, v3);
+            bc[r] = ((v0 + v1) + v2) + v3;
         }
         return;
     }
-    // outer faces (outside column, stored face index), two per child in child order:
+    // outer faces: tiled offset of the outside column and offset of the face
+    // in kh, two per child in child order:
     //   child (0,0): W, S   child (1,0): E, S   child (0,1): W, N   child (1,1): E, N
-    int out[8], fc[8];
+    int out[8];
+    uint32_t fc[8];
     {
         const int c00 = ch[0], c10 = ch[1], c01 = ch[2], c11 = ch[3];
+        const uint32_t nvu = uint32_t(nv);
         out[0] = F.nbr[1 * ncol + c00]; fc[0] = F.fface[c00];
         out[1] = F.nbr[3 * ncol + c00]; fc[1] = F.fface[ncol + c00];
-        out[2] = F.nbr[0 * ncol + c10]; fc[2] = c10;
+        out[2] = F.nbr[0 * ncol + c10]; fc[2] = uint32_t(cb[1]);
         out[3] = F.nbr[3 * ncol + c10]; fc[3] = F.fface[ncol + c10];
         out[4] = F.nbr[1 * ncol + c01]; fc[4] = F.fface[c01];
-        out[5] = F.nbr[2 * ncol + c01]; fc[5] = ncol + c01;
-        out[6] = F.nbr[0 * ncol + c11]; fc[6] = c11;
-        out[7] = F.nbr[2 * ncol + c11]; fc[7] = ncol + c11;
+        out[5] = F.nbr[2 * ncol + c01]; fc[5] = nvu + uint32_t(cb[2]);
+        out[6] = F.nbr[0 * ncol + c11]; fc[6] = uint32_t(cb[3]);
+        out[7] = F.nbr[2 * ncol + c11]; fc[7] = nvu + uint32_t(cb[3]);
+#pragma unroll
+        for (int f = 0; f < 8; ++f) out[f] = tile_base(out[f], nz);
     }
     T xdn[4] = {T(0), T(0), T(0), T(0)}, xo[4], kvdn[4] = {T(0), T(0), T(0), T(0)};
     if (k0 > 0) {
-        const int64_t rdn = int64_t(k0 - 1) * ncol;
-        load_pair<T, PAIR>(x, rdn + ch[0], xdn[0], xdn[1]);
-        load_pair<T, PAIR>(x, rdn + ch[2], xdn[2], xdn[3]);
-        load_pair<T, PAIR>(F.kv, rdn + ch[0], kvdn[0], kvdn[1]);
-        load_pair<T, PAIR>(F.kv, rdn + ch[2], kvdn[2], kvdn[3]);
+        const int rdn = kTile * (k0 - 1);
+        load_pair<T, PAIR>(x, rdn + cb[0], xdn[0], xdn[1]);
+        load_pair<T, PAIR>(x, rdn + cb[2], xdn[2], xdn[3]);
+        load_pair<T, PAIR>(F.kv, rdn + cb[0], kvdn[0], kvdn[1]);
+        load_pair<T, PAIR>(F.kv, rdn + cb[2], kvdn[2], kvdn[3]);
     }
-    load_pair<T, PAIR>(x, int64_t(k0) * ncol + ch[0], xo[0], xo[1]);
-    load_pair<T, PAIR>(x, int64_t(k0) * ncol + ch[2], xo[2], xo[3]);
+    load_pair<T, PAIR>(x, kTile * k0 + cb[0], xo[0], xo[1]);
+    load_pair<T, PAIR>(x, kTile * k0 + cb[2], xo[2], xo[3]);
     for (int k = k0; k < k1; ++k) {
-        const int64_t row = int64_t(k) * ncol;
-        const T* kh = F.kh + 2 * row;
+        const int r = kTile * k;
         T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8];
         if (k + 1 < nz) {
-            load_pair<T, PAIR>(x, row + ncol + ch[0], xup[0], xup[1]);
-            load_pair<T, PAIR>(x, row + ncol + ch[2], xup[2], xup[3]);
+            load_pair<T, PAIR>(x, r + kTile + cb[0], xup[0], xup[1]);
+            load_pair<T, PAIR>(x, r + kTile + cb[2], xup[2], xup[3]);
         }
-        load_pair<T, PAIR>(b, row + ch[0], vb[0], vb[1]);
-        load_pair<T, PAIR>(b, row + ch[2], vb[2], vb[3]);
-        load_pair<T, PAIR>(F.dl, row + ch[0], vd[0], vd[1]);
-        load_pair<T, PAIR>(F.dl, row + ch[2], vd[2], vd[3]);
-        load_pair<T, PAIR>(F.kv, row + ch[0], vkv[0], vkv[1]);
-        load_pair<T, PAIR>(F.kv, row + ch[2], vkv[2], vkv[3]);
+        load_pair<T, PAIR>(b, r + cb[0], vb[0], vb[1]);
+        load_pair<T, PAIR>(b, r + cb[2], vb[2], vb[3]);
+        load_pair<T, PAIR>(F.dl, r + cb[0], vd[0], vd[1]);
+        load_pair<T, PAIR>(F.dl, r + cb[2], vd[2], vd[3]);
+        load_pair<T, PAIR>(F.kv, r + cb[0], vkv[0], vkv[1]);
+        load_pair<T, PAIR>(F.kv, r + cb[2], vkv[2], vkv[3]);
 #pragma unroll
         for (int f = 0; f < 8; ++f) {
-            vxo[f] = x[row + out[f]];
-            vk[f] = kh[fc[f]];
+            vxo[f] = x[out[f] + r];
+            vk[f] = F.kh[fc[f] + uint32_t(r)];
         }
         T acc = ((vb[0] + vb[1]) + vb[2]) + vb[3];
 #pragma unroll
@@ -639,7 +680,7 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
         }
 #pragma unroll
         for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
-        bc[int64_t(k) * ncol_c + C] = acc;
+        bc[r] = acc;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             xdn[s] = xo[s];
@@ -653,16 +694,17 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c,
 // post-smoothing sweep to fuse it into): y = x + xc[parent] (x may be null).
 template <typename T>
 __global__ void __launch_bounds__(kBlock)
-k_prolong(int ncol, int nz, int ncol_c, const int32_t* __restrict__ parent, const T* __restrict__ x,
-          const T* __restrict__ xc, T* __restrict__ y, int64_t total) {
+k_prolong(int ncol, int nz, int nvp, int nvp_c, const int32_t* __restrict__ parent,
+          const T* __restrict__ x, const T* __restrict__ xc, T* __restrict__ y, int64_t total) {
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * kBlock) {
         const int64_t per = int64_t(nz) * ncol;
         const int64_t rhs = i / per, rem = i % per;
-        const int64_t k = rem / ncol;
+        const int k = int(rem / ncol);
         const int c = int(rem % ncol);
-        const T v = xc[rhs * int64_t(nz) * ncol_c + k * ncol_c + parent[c]];
-        y[i] = x ? x[i] + v : v;
+        const T v = xc[rhs * nvp_c + tile_base(parent[c], nz) + kTile * k];
+        const int64_t o = rhs * nvp + tile_base(c, nz) + kTile * k;
+        y[o] = x ? x[o] + v : v;
     }
 }
 
@@ -671,21 +713,23 @@ k_prolong(int ncol, int nz, int ncol_c, const int32_t* __restrict__ parent, cons
 
 // ABI layout -> internal layout on the finest level.
 __global__ void __launch_bounds__(kBlock)
-k_setup_fine(int ncol, int nz, const double* __restrict__ kh_in, const double* __restrict__ kv_in,
-             const double* __restrict__ dl_in, double* __restrict__ kh, double* __restrict__ kv,
-             double* __restrict__ dl, int* __restrict__ flags) {
+k_setup_fine(int ncol, int nz, int nvp, const double* __restrict__ kh_in,
+             const double* __restrict__ kv_in, const double* __restrict__ dl_in,
+             double* __restrict__ kh, double* __restrict__ kv, double* __restrict__ dl,
+             int* __restrict__ flags) {
     const int64_t total = int64_t(nz) * ncol;
     int bad = 0;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * kBlock) {
-        const int64_t k = i / ncol, c = i % ncol;
+        const int k = int(i / ncol), c = int(i % ncol);
         const double e = kh_in[i], n = kh_in[total + i];
         const double v = (k + 1 < nz) ? kv_in[i] : 0.0;
         const double d = dl_in[i];
-        kh[2 * k * ncol + c] = e;
-        kh[2 * k * ncol + ncol + c] = n;
-        kv[i] = v;
-        dl[i] = d;
+        const int o = tile_base(c, nz) + kTile * k;
+        kh[o] = e;
+        kh[int64_t(nvp) + o] = n;
+        kv[o] = v;
+        dl[o] = d;
         if (!isfinite(e) || !isfinite(n) || !isfinite(v) || !isfinite(d)) bad |= 1;
         if (!(e >= 0.0) || !(n >= 0.0) || !(v >= 0.0) || !(d > 0.0)) bad |= 2;
     }
@@ -696,23 +740,25 @@ k_setup_fine(int ncol, int nz, const double* __restrict__ kh_in, const double* _
 // Eq. DH_ratios): coarse E face = mean of the E faces of children (1,0),(1,1);
 // N face = mean of the N faces of (0,1),(1,1); kv and delta summed over all four.
 __global__ void __launch_bounds__(kBlock)
-k_coarsen(int ncol_f, int ncol_c, int nz, const int32_t* __restrict__ child,
+k_coarsen(int ncol_c, int nz, int nvp_f, int nvp_c, const int32_t* __restrict__ child,
           const double* __restrict__ khf, const double* __restrict__ kvf,
           const double* __restrict__ dlf, double* __restrict__ khc, double* __restrict__ kvc,
           double* __restrict__ dlc) {
     const int64_t total = int64_t(nz) * ncol_c;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * kBlock) {
-        const int64_t k = i / ncol_c;
+        const int k = int(i / ncol_c);
         const int C = int(i % ncol_c);
-        const int c00 = child[C], c10 = child[ncol_c + C], c01 = child[2 * ncol_c + C],
-                  c11 = child[3 * ncol_c + C];
-        const double* kf = khf + 2 * k * ncol_f;
-        khc[2 * k * ncol_c + C] = 0.5 * (kf[c10] + kf[c11]);
-        khc[2 * k * ncol_c + ncol_c + C] = 0.5 * (kf[ncol_f + c01] + kf[ncol_f + c11]);
-        const int64_t r = k * ncol_f;
-        kvc[i] = ((kvf[r + c00] + kvf[r + c10]) + kvf[r + c01]) + kvf[r + c11];
-        dlc[i] = ((dlf[r + c00] + dlf[r + c10]) + dlf[r + c01]) + dlf[r + c11];
+        const int r = kTile * k;
+        const int c00 = tile_base(child[C], nz) + r, c10 = tile_base(child[ncol_c + C], nz) + r,
+                  c01 = tile_base(child[2 * ncol_c + C], nz) + r,
+                  c11 = tile_base(child[3 * ncol_c + C], nz) + r;
+        const int o = tile_base(C, nz) + r;
+        const double* khfN = khf + nvp_f;
+        khc[o] = 0.5 * (khf[c10] + khf[c11]);
+        khc[int64_t(nvp_c) + o] = 0.5 * (khfN[c01] + khfN[c11]);
+        kvc[o] = ((kvf[c00] + kvf[c10]) + kvf[c01]) + kvf[c11];
+        dlc[o] = ((dlf[c00] + dlf[c10]) + dlf[c01]) + dlf[c11];
     }
 }
 
@@ -722,12 +768,19 @@ k_factor(LevelView<double> L, int mid, double* __restrict__ cc, double* __restri
     const int ncol = L.ncol, nz = L.nz;
     const int c = blockIdx.x * kBlock + threadIdx.x;
     if (c >= ncol) return;
-    const int fW = L.fface[c], fS = L.fface[ncol + c];
+    const uint32_t fW = L.fface[c], fS = L.fface[ncol + c];
+    const int ob = tile_base(c, nz);
+    const double* khN = L.kh + L.nvp;
     auto s_of = [&](int k) {
-        const double* kh = L.kh + 2 * int64_t(k) * ncol;
-        return L.dl[int64_t(k) * ncol + c] + kh[c] + kh[fW] + kh[ncol + c] + kh[fS];
+        const int o = ob + kTile * k;
+        return L.dl[o] + L.kh[o] + L.kh[fW + uint32_t(kTile * k)] + khN[o] +
+               L.kh[fS + uint32_t(kTile * k)];
     };
-    auto kv_of = [&](int k) { return L.kv[int64_t(k) * ncol + c]; };
+    auto kv_of = [&](int k) { return L.kv[ob + kTile * k]; };
+    auto put = [&](int k, double m, double cv) {
+        mm[ob + kTile * k] = m;
+        cc[ob + kTile * k] = cv;
+    };
     const int top_end = mid < nz ? mid : nz;  // rows [0, top_end) top-down
     double e = 0.0;
     for (int k = 0; k < top_end; ++k) {
@@ -740,8 +793,7 @@ k_factor(LevelView<double> L, int mid, double* __restrict__ cc, double* __restri
         }
         const double kvk = kv_of(k);
         const double m = 1.0 / (e + kvk);
-        mm[int64_t(k) * ncol + c] = m;
-        cc[int64_t(k) * ncol + c] = kvk * m;
+        put(k, m, kvk * m);
     }
     if (mid >= nz) return;
     double f = 0.0;
@@ -755,8 +807,7 @@ k_factor(LevelView<double> L, int mid, double* __restrict__ cc, double* __restri
         }
         const double up = kv_of(k - 1);
         const double m = 1.0 / (f + up);
-        mm[int64_t(k) * ncol + c] = m;
-        cc[int64_t(k) * ncol + c] = up * m;
+        put(k, m, up * m);
     }
     double tau = s_of(mid);
     if (mid > 0) {
@@ -767,8 +818,7 @@ k_factor(LevelView<double> L, int mid, double* __restrict__ cc, double* __restri
         const double a = kv_of(mid);
         tau += a * f / (f + a);
     }
-    mm[int64_t(mid) * ncol + c] = 1.0 / tau;
-    cc[int64_t(mid) * ncol + c] = 0.0;
+    put(mid, 1.0 / tau, 0.0);
 }
 
 template <typename S, typename D>
@@ -785,51 +835,91 @@ k_convert(const S* __restrict__ src, D* __restrict__ dst, int64_t n) {
 // right-hand side adds the partials in a fixed order and derives the CG
 // scalar, so repeated runs give identical bits.
 //
-// x = 0, r = b, r32 = float(b); partial ||b||^2.
+// Kernels that meet a vector in the ABI layout run one workgroup per
+// (right-hand side, tile): thread (lc, g) visits levels g, g + 8, ... of
+// column tile * 32 + lc, so the tiled side is read as contiguous rows and the
+// ABI side as 32-column row pieces.
+struct TileGrid {
+    int rhs, tile, lc, g, c;
+    bool valid;
+};
+__device__ __forceinline__ TileGrid tile_grid(int ncol) {
+    const int ntile = (ncol + kTile - 1) / kTile;
+    TileGrid t;
+    t.rhs = blockIdx.x / ntile;
+    t.tile = blockIdx.x % ntile;
+    t.lc = threadIdx.x & (kTile - 1);
+    t.g = threadIdx.x / kTile;
+    t.c = t.tile * kTile + t.lc;
+    t.valid = t.c < ncol;
+    return t;
+}
+constexpr int kTileGroups = kBlock / kTile;
+
+// x = 0, r = b, r32 = float(b) (b and x in the ABI layout); partial ||b||^2
+// per tile.
 __global__ void __launch_bounds__(kBlock)
 k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
-          float* __restrict__ r32, int64_t n, int nblk, CgState st) {
+          float* __restrict__ r32, int ncol, int nz, int nvp, CgState st) {
     __shared__ double sh[kBlock / 64];
-    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
-    int64_t i0, i1;
-    grid_range(n, nblk, blk, i0, i1);
-    const int64_t off = int64_t(rhs) * n;
+    const TileGrid t = tile_grid(ncol);
+    const int64_t n = int64_t(nz) * ncol;
     double acc = 0.0;
-#pragma unroll 4
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        const double v = b[off + i];
-        x[off + i] = 0.0;
-        r[off + i] = v;
-        if (r32) r32[off + i] = float(v);
-        acc += v * v;
+    if (t.valid) {
+        const int64_t ia = t.rhs * n + t.c, it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
+        for (int k = t.g; k < nz; k += kTileGroups) {
+            const double v = b[ia + int64_t(k) * ncol];
+            x[ia + int64_t(k) * ncol] = 0.0;
+            r[it + kTile * k] = v;
+            if (r32) r32[it + kTile * k] = float(v);
+            acc += v * v;
+        }
     }
     const double s = block_sum(acc, sh);
-    store_partial(st, rhs, blk, s, 0.0, false);
+    store_partial(st, t.rhs, t.tile, s, 0.0, false);
 }
 
-// x += alpha p; r -= alpha q; r32 = float(r); partial ||r||^2.
+// x += alpha p (x in the ABI layout); r -= alpha q; r32 = float(r); partial
+// ||r||^2 per tile.
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
-            const double* __restrict__ p, const double* __restrict__ q, int64_t n, int nblk,
+            const double* __restrict__ p, const double* __restrict__ q, int ncol, int nz, int nvp,
             CgState st) {
     __shared__ double sh[kBlock / 64];
-    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
-    if (!st.active[rhs]) return;
-    const double alpha = st.sc[rhs * 8 + kAlpha];
-    int64_t i0, i1;
-    grid_range(n, nblk, blk, i0, i1);
-    const int64_t off = int64_t(rhs) * n;
+    const TileGrid t = tile_grid(ncol);
+    if (!st.active[t.rhs]) return;
+    const double alpha = st.sc[t.rhs * 8 + kAlpha];
+    const int64_t n = int64_t(nz) * ncol;
     double acc = 0.0;
-#pragma unroll 4
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        x[off + i] += alpha * p[off + i];
-        const double v = r[off + i] - alpha * q[off + i];
-        r[off + i] = v;
-        if (r32) r32[off + i] = float(v);
-        acc += v * v;
+    if (t.valid) {
+        const int64_t ia = t.rhs * n + t.c, it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
+        for (int k = t.g; k < nz; k += kTileGroups) {
+            const int64_t o = it + kTile * k;
+            x[ia + int64_t(k) * ncol] += alpha * p[o];
+            const double v = r[o] - alpha * q[o];
+            r[o] = v;
+            if (r32) r32[o] = float(v);
+            acc += v * v;
+        }
     }
     const double s = block_sum(acc, sh);
-    store_partial(st, rhs, blk, s, 0.0, false);
+    store_partial(st, t.rhs, t.tile, s, 0.0, false);
+}
+
+// Layout conversion between the ABI layout and the tiled one, with a cast.
+template <typename S, typename D, bool TO_TILED>
+__global__ void __launch_bounds__(kBlock)
+k_retile(const S* __restrict__ src, D* __restrict__ dst, int ncol, int nz, int nvp) {
+    const TileGrid t = tile_grid(ncol);
+    if (!t.valid) return;
+    const int64_t n = int64_t(nz) * ncol;
+    const int64_t ia = t.rhs * n + t.c, it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
+    for (int k = t.g; k < nz; k += kTileGroups) {
+        if (TO_TILED)
+            dst[it + kTile * k] = D(src[ia + int64_t(k) * ncol]);
+        else
+            dst[ia + int64_t(k) * ncol] = D(src[it + kTile * k]);
+    }
 }
 
 // partial r . z (and z . q for the flexible beta).
