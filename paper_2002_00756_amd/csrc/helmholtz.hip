@@ -743,7 +743,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     const bool flex = h->cfg.cg_variant == HELMHOLTZ_CG_FLEXIBLE;
     float* r32 = mixed ? h->lev[0].f.b : nullptr;
     float* z32 = mixed ? h->lev[0].f.x : nullptr;
-    const dim3 red(kRedBlocks * batch), blk(kBlock);
+    const dim3 red(kRedBlocks * batch), blk(kBlock), fin(kFinBlock);
     const CgState st = cg_state(h);
 
     // the host mirror doubles as staging for the initial scalars
@@ -756,7 +756,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
                             hipMemcpyHostToDevice, s));
     // x = 0, r = b, ||b||^2
     hipLaunchKernelGGL(k_cg_init, tgrid, blk, 0, s, b, x, h->r, r32, v0.ncol, h->nz, v0.nvp, st);
-    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinBB), ntile32, 0);
+    hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBB), ntile32, 0);
     if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
     std::vector<int> need(batch, 1);
     if (int e = wait_published(h, s, need, 0)) return e;
@@ -787,7 +787,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     else
         hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, nullptr, n,
                            kRedBlocks, st);
-    hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinRho), kRedBlocks, 0);
+    hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRho), kRedBlocks, 0);
     if (mixed)
         hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks, h->sc,
                            h->active, 1);
@@ -803,12 +803,12 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         for (int i = 0; i < batch; ++i) was_active[i] = h->hact[i];
         // q = H p, alpha = rho / p.q
         launch_apply<double>(h, 0, h->p, h->q, batch, true, h->active, s);
-        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
+        hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
                            0);
         // x += alpha p, r -= alpha q, ||r||^2 and the convergence flags, published
         hipLaunchKernelGGL(k_cg_update, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q, v0.ncol,
                            h->nz, v0.nvp, st);
-        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st, int(kFinRR), ntile32, iter);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRR), ntile32, iter);
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
         if (int e = wait_published(h, s, was_active, iter)) return e;
         bool still = false;
@@ -834,7 +834,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         else
             hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, qarg, n,
                                kRedBlocks, st);
-        hipLaunchKernelGGL(k_finalize, dim3(batch), blk, 0, s, st,
+        hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st,
                            int(flex ? kFinBetaFlex : kFinBeta), kRedBlocks, 0);
         if (mixed)
             hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks,

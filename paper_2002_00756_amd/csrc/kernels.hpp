@@ -111,9 +111,67 @@ enum SweepMode { kZero = 0, kPlain = 1, kProlong = 2, kProlongZero = 3 };
 // Two lanes per column (tid < ncol: rows above mid, top-down; BOT <= tid <
 // BOT + ncol: rows below mid, bottom-up) walk the column, SEQ levels per LDS
 // round trip; row mid combines both eliminations. E1, E2 hold ncol values.
-// The SEQ reads of a round trip use row indices clamped into the walker's
-// own half of the column, so they are unconditional and issue together; the
-// range test only guards the arithmetic and the stores.
+//
+// Each walk is a run of rows k = first + dir * i, i < count, with a
+// first-order recurrence along it. Full batches of SEQ rows carry no range
+// tests, so their SEQ reads issue together and the recurrence is a plain
+// chain of fused multiply-adds; the last, partial batch reads row indices
+// clamped into the run and tests only the arithmetic and the stores.
+template <typename T, int SEQ, bool ELIM>
+__device__ __forceinline__ T walk(T* R, const T* Cf, int S, int lane, int first, int dir,
+                                  int count, T v, T& carry) {
+    // ELIM: t_k = r_k + carry * t_prev, carry <- cf_k   (elimination; v = t)
+    // else: z_k = r_k + cf_k * z_prev                     (substitution; v = z)
+    int i0 = 0;
+    for (; i0 + SEQ <= count; i0 += SEQ) {
+        T rr[SEQ], cf[SEQ];
+#pragma unroll
+        for (int i = 0; i < SEQ; ++i) {
+            const int k = first + dir * (i0 + i);
+            rr[i] = R[k * S + lane];
+            cf[i] = Cf[k * S + lane];
+        }
+#pragma unroll
+        for (int i = 0; i < SEQ; ++i) {
+            if (ELIM) {
+                v = rr[i] + carry * v;
+                carry = cf[i];
+            } else {
+                v = rr[i] + cf[i] * v;
+            }
+            rr[i] = v;
+        }
+#pragma unroll
+        for (int i = 0; i < SEQ; ++i) R[(first + dir * (i0 + i)) * S + lane] = rr[i];
+    }
+    if (i0 < count) {
+        const int last = count - 1;
+        T rr[SEQ], cf[SEQ];
+#pragma unroll
+        for (int i = 0; i < SEQ; ++i) {
+            const int k = first + dir * min(i0 + i, last);
+            rr[i] = R[k * S + lane];
+            cf[i] = Cf[k * S + lane];
+        }
+#pragma unroll
+        for (int i = 0; i < SEQ; ++i) {
+            if (i0 + i < count) {
+                if (ELIM) {
+                    v = rr[i] + carry * v;
+                    carry = cf[i];
+                } else {
+                    v = rr[i] + cf[i] * v;
+                }
+                rr[i] = v;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < SEQ; ++i)
+            if (i0 + i < count) R[(first + dir * (i0 + i)) * S + lane] = rr[i];
+    }
+    return v;
+}
+
 template <typename T, int JMAX>
 __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T (&mo)[JMAX],
                                              int tid, int lc, int kg, int KG, int BOT, int mid,
@@ -121,51 +179,13 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
     constexpr int SEQ = 8;
     // ---- phase 2: eliminate towards row mid -------------------------------
     if (tid < ncol) {
-        T t = T(0), cp = T(0);
-        for (int k0 = 0; k0 < mid; k0 += SEQ) {
-            T rr[SEQ], cf[SEQ];
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                const int k = min(k0 + i, mid - 1);
-                rr[i] = R[k * S + tid];
-                cf[i] = Cf[k * S + tid];
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                if (k0 + i < mid) {
-                    t = rr[i] + cp * t;
-                    rr[i] = t;
-                    cp = cf[i];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i)
-                if (k0 + i < mid) R[(k0 + i) * S + tid] = rr[i];
-        }
+        T cp = T(0);
+        const T t = walk<T, SEQ, true>(R, Cf, S, tid, 0, 1, mid, T(0), cp);
         E1[tid] = cp * t;
     } else if (tid >= BOT && tid < BOT + ncol) {
         const int l2 = tid - BOT;
-        T t = T(0), cn = T(0);
-        for (int k0 = nz - 1; k0 > mid; k0 -= SEQ) {
-            T rr[SEQ], cf[SEQ];
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                const int k = max(k0 - i, mid + 1);
-                rr[i] = R[k * S + l2];
-                cf[i] = Cf[k * S + l2];
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                if (k0 - i > mid) {
-                    t = rr[i] + cn * t;
-                    rr[i] = t;
-                    cn = cf[i];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i)
-                if (k0 - i > mid) R[(k0 - i) * S + l2] = rr[i];
-        }
+        T cn = T(0);
+        const T t = walk<T, SEQ, true>(R, Cf, S, l2, nz - 1, -1, nz - 1 - mid, T(0), cn);
         E2[l2] = cn * t;
     }
     __syncthreads();
@@ -185,49 +205,12 @@ __device__ __forceinline__ void column_solve(T* R, T* Cf, T* E1, T* E2, const T 
     __syncthreads();
 
     // ---- phase 4: back substitution outwards from row mid ----------------
+    T unused = T(0);
     if (tid < ncol) {
-        T z = R[mid * S + tid];
-        for (int k0 = mid - 1; k0 >= 0; k0 -= SEQ) {
-            T rr[SEQ], cf[SEQ];
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                const int k = max(k0 - i, 0);
-                rr[i] = R[k * S + tid];
-                cf[i] = Cf[k * S + tid];
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                if (k0 - i >= 0) {
-                    z = rr[i] + cf[i] * z;
-                    rr[i] = z;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i)
-                if (k0 - i >= 0) R[(k0 - i) * S + tid] = rr[i];
-        }
+        walk<T, SEQ, false>(R, Cf, S, tid, mid - 1, -1, mid, R[mid * S + tid], unused);
     } else if (tid >= BOT && tid < BOT + ncol) {
         const int l2 = tid - BOT;
-        T z = R[mid * S + l2];
-        for (int k0 = mid + 1; k0 < nz; k0 += SEQ) {
-            T rr[SEQ], cf[SEQ];
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                const int k = min(k0 + i, nz - 1);
-                rr[i] = R[k * S + l2];
-                cf[i] = Cf[k * S + l2];
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i) {
-                if (k0 + i < nz) {
-                    z = rr[i] + cf[i] * z;
-                    rr[i] = z;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < SEQ; ++i)
-                if (k0 + i < nz) R[(k0 + i) * S + l2] = rr[i];
-        }
+        walk<T, SEQ, false>(R, Cf, S, l2, mid + 1, 1, nz - 1 - mid, R[mid * S + l2], unused);
     }
     __syncthreads();
 }
@@ -298,7 +281,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     };
     // Loads of CH levels are issued together before any is used, so each
     // thread keeps several rows of independent loads in flight.
-    constexpr int CH = CH_ > 0 ? CH_ : (MODE == kZero ? 8 : (kHasP || sizeof(T) == 8 ? 2 : 3));
+    constexpr int CH = CH_ > 0 ? CH_ : (MODE == kZero ? 8 : 2);
     T xo[JMAX], mo[JMAX];
 #pragma unroll
     for (int j0 = 0; j0 < JMAX; j0 += CH) {
@@ -408,11 +391,20 @@ __device__ __forceinline__ void grid_range(int64_t n, int nblk, int blk, int64_t
     i1 = min(n, i0 + per);
 }
 
-// Sum `cnt` partials in a fixed order (result in every thread).
+// Sum `cnt` partials in a fixed order (result in every thread). Four
+// independent accumulators per thread keep several loads in flight.
 __device__ __forceinline__ double reduce_partials(const double* part, int cnt, double* sh) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) acc += part[i];
-    const double s = block_sum(acc, sh);
+    const int step = blockDim.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = threadIdx.x;
+    for (; i + 3 * step < cnt; i += 4 * step) {
+        a0 += part[i];
+        a1 += part[i + step];
+        a2 += part[i + 2 * step];
+        a3 += part[i + 3 * step];
+    }
+    for (; i < cnt; i += step) a0 += part[i];
+    const double s = block_sum((a0 + a1) + (a2 + a3), sh);
     __syncthreads();
     if (threadIdx.x == 0) sh[0] = s;
     __syncthreads();
@@ -431,9 +423,11 @@ __device__ __forceinline__ void store_partial(const CgState& st, int rhs, int bl
 // One block per right-hand side: add the `cnt` partials in a fixed order and
 // derive the CG scalar. The norm reductions (kFinBB, kFinRR) also publish the
 // scalars and flags to the host mirror, then the sequence number `seq`.
-__global__ void __launch_bounds__(kBlock)
+constexpr int kFinBlock = 1024;  // threads of the finalisation block
+
+__global__ void __launch_bounds__(kFinBlock)
 k_finalize(CgState st, int mode, int cnt, int seq) {
-    __shared__ double sh[kBlock / 64];
+    __shared__ double sh[kFinBlock / 64];
     const int rhs = blockIdx.x;
     if (mode != kFinBB && !st.active[rhs]) return;
     const bool two = mode == kFinBetaFlex;
