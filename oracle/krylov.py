@@ -2,12 +2,14 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-Section 4.1 lists CG(A, P, eps) among the Krylov solvers that take a linear
-operator A and a preconditioner P; the preconditioner here is one V-cycle from
-a zero guess (Section 3.6), or, with one level, block-Jacobi sweeps
-(P_H^(Jac)). The synthetic operator is symmetric positive definite and so is
-the V-cycle with equal pre- and post-smoothing, so CG applies. Convergence is
-judged on the recursively updated residual, ||r|| <= rtol ||b||, from x = 0.
+Section 4.1 lists CG(A, P, eps) and BiCGStab(A, P, eps) among the Krylov
+solvers that take a linear operator A and a preconditioner P; the
+preconditioner here is one V-cycle from a zero guess (Section 3.6), or, with
+one level, block-Jacobi sweeps (P_H^(Jac)). The synthetic operator is
+symmetric positive definite and so is the V-cycle with equal pre- and
+post-smoothing, so CG applies; BiCGStab does not need the symmetry.
+Convergence is judged on the recursively updated residual,
+||r|| <= rtol ||b||, from x = 0.
 
 The float32 form keeps the outer loop in float64 and runs only the
 preconditioner in float32 (its input rounded from float64, its coefficients
@@ -69,6 +71,59 @@ def pcg(apply_A, apply_M, b, rtol=1e-8, maxiter=200, flexible=False) -> CGResult
         rho = rho_new
 
 
+def bicgstab(apply_A, apply_M, b, rtol=1e-8, maxiter=200) -> CGResult:
+    """Right-preconditioned BiCGStab from x = 0 (van der Vorst's method).
+
+    Section 4.1 lists BiCGStab(A, P, eps) among the solvers; the paper's cost
+    model gives each iteration two products with H and two preconditioner
+    applications, and four global sums (Section 3.7): here (r0, v), the pair
+    (t, s), (t, t), and (r0, r) with ||r|| for the next step and the
+    convergence test. The shadow residual r0 is the initial residual b.
+    Convergence: ||r|| <= rtol ||b|| on the recursively updated residual.
+    A zero (r0, v), or a zero (r0, r) or omega before convergence, is a
+    breakdown: the iteration stops there, not converged. ``iters`` counts
+    iterations (two products with A each).
+    """
+    x = np.zeros_like(b)
+    bnorm = float(np.linalg.norm(b))
+    if bnorm == 0.0:
+        return CGResult(x, 0, 0.0, True, [0.0])
+    r = b.copy()
+    r0 = b.copy()
+    rho = float(np.vdot(r0, r))
+    p = r.copy()
+    v = np.zeros_like(b)
+    hist = [1.0]
+    it = 0
+    while True:
+        ph = apply_M(p)
+        v = apply_A(ph)
+        rv = float(np.vdot(r0, v))
+        if rv == 0.0:
+            return CGResult(x, it, hist[-1], False, hist)
+        alpha = rho / rv
+        s = r - alpha * v
+        sh = apply_M(s)
+        t = apply_A(sh)
+        tt = float(np.vdot(t, t))
+        omega = float(np.vdot(t, s)) / tt if tt > 0.0 else 0.0
+        x = x + alpha * ph + omega * sh
+        r = s - omega * t
+        it += 1
+        rel = float(np.linalg.norm(r)) / bnorm
+        hist.append(rel)
+        if rel <= rtol:
+            return CGResult(x, it, rel, True, hist)
+        if it >= maxiter:
+            return CGResult(x, it, rel, False, hist)
+        rho_new = float(np.vdot(r0, r))
+        if rho_new == 0.0 or omega == 0.0:
+            return CGResult(x, it, rel, False, hist)
+        beta = (rho_new / rho) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        rho = rho_new
+
+
 def mg_preconditioner(hier, params: MGParams = MGParams()):
     """x = M r: one V-cycle from zero on ``hier`` (float64)."""
     return lambda r: vcycle(hier, r, params)
@@ -85,8 +140,13 @@ def mg_preconditioner_f32(hier, params: MGParams = MGParams()):
 
 
 def solve(hier, b, rtol=1e-8, maxiter=200, params: MGParams = MGParams(),
-          precision="fp64", flexible=False) -> CGResult:
-    """MG-preconditioned CG for H x = b on the finest level of ``hier``."""
+          precision="fp64", flexible=False, method="cg") -> CGResult:
+    """MG-preconditioned CG (or BiCGStab, ``method="bicgstab"``) for H x = b on
+    the finest level of ``hier``. With one level the preconditioner is
+    P_H^(Jac)(omega, n_coarse)."""
     M = mg_preconditioner_f32(hier, params) if precision == "fp32" else \
         mg_preconditioner(hier, params)
-    return pcg(lambda v: hier.apply(0, v), M, b, rtol, maxiter, flexible)
+    A = lambda v: hier.apply(0, v)  # noqa: E731
+    if method == "bicgstab":
+        return bicgstab(A, M, b, rtol, maxiter)
+    return pcg(A, M, b, rtol, maxiter, flexible)

@@ -100,3 +100,77 @@ def test_block_jacobi_pcg_needs_more_iterations():
     bj = krylov.solve(h1, b, rtol=1e-6, params=MGParams(omega=1.0, n_coarse=1))
     assert mg.converged and bj.converged
     assert bj.iters > mg.iters
+
+
+# ---- BiCGStab (Section 4.1) -------------------------------------------------
+
+def _nonsymmetric(n, seed):
+    """Diagonally dominant, clearly non-symmetric test matrix."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(-1.0, 1.0, (n, n))
+    A += np.diag(np.abs(A).sum(axis=1) + 1.0)
+    return A
+
+
+def test_bicgstab_iterates_match_scipy():
+    """Same algorithm (right preconditioning, shadow residual b, x0 = 0): the
+    iterate after k steps agrees with SciPy's to rounding, for k = 1..6, on a
+    non-symmetric matrix with a non-trivial preconditioner (Jacobi)."""
+    n = 40
+    A = _nonsymmetric(n, 5)
+    b = np.random.default_rng(6).standard_normal(n)
+    d = 1.0 / np.diag(A)
+    M = spla.LinearOperator((n, n), matvec=lambda v: d * v)
+    for k in range(1, 7):
+        ref, _ = spla.bicgstab(A, b, rtol=1e-300, atol=0.0, maxiter=k, M=M)
+        res = krylov.bicgstab(lambda v: A @ v, lambda v: d * v, b, rtol=0.0, maxiter=k)
+        assert res.iters == k
+        assert np.linalg.norm(res.x - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_bicgstab_converges_to_dense_solve():
+    n = 60
+    A = _nonsymmetric(n, 7)
+    b = np.random.default_rng(8).standard_normal(n)
+    res = krylov.bicgstab(lambda v: A @ v, lambda v: v, b, rtol=1e-13, maxiter=200)
+    ref = np.linalg.solve(A, b)
+    assert res.converged
+    assert np.linalg.norm(A @ res.x - b) <= 1e-13 * np.linalg.norm(b) * 1.0001
+    assert np.linalg.norm(res.x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_bicgstab_exact_preconditioner_one_step():
+    """With P = A^-1: p_hat = A^-1 b, v = b, alpha = 1, s = 0, t = 0, omega = 0,
+    so one step gives x = A^-1 b exactly up to rounding."""
+    n = 30
+    A = _nonsymmetric(n, 9)
+    Ainv = np.linalg.inv(A)
+    b = np.random.default_rng(10).standard_normal(n)
+    res = krylov.bicgstab(lambda v: A @ v, lambda v: Ainv @ v, b, rtol=1e-10, maxiter=5)
+    assert res.converged and res.iters == 1
+    assert np.linalg.norm(res.x - np.linalg.solve(A, b)) <= 1e-12 * np.linalg.norm(res.x)
+
+
+def test_bicgstab_zero_rhs_and_maxiter():
+    A = _nonsymmetric(20, 11)
+    res = krylov.bicgstab(lambda v: A @ v, lambda v: v, np.zeros(20))
+    assert res.converged and res.iters == 0 and not res.x.any()
+    b = np.ones(20)
+    res = krylov.bicgstab(lambda v: A @ v, lambda v: v, b, rtol=0.0, maxiter=3)
+    assert not res.converged and res.iters == 3
+
+
+@pytest.mark.parametrize("L", [1, 3])
+def test_bicgstab_mg_and_jacobi_on_helmholtz(L):
+    """BiCGStab + MG(L) (L = 1: P_Jac(1, 1)) on the C12 operator converges to the
+    dense solution; the MG-preconditioned one needs far fewer iterations."""
+    w = workloads.Workload("t", 12, 10, 1.0, 100.0, False, L)
+    hier = _hier(w)
+    b = workloads.rhs(w.N, w.nz)[0]
+    prm = MGParams() if L > 1 else MGParams(omega=1.0, n_coarse=1)
+    res = krylov.solve(hier, b, rtol=1e-11, params=prm, method="bicgstab", maxiter=400)
+    H = helmholtz.assemble(hier.levels[0], *hier.coeffs[0]).tocsc()
+    ref = spla.spsolve(H, b.ravel()).reshape(b.shape)
+    assert res.converged
+    assert np.linalg.norm(res.x - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert res.iters <= (8 if L > 1 else 400)
