@@ -8,7 +8,8 @@
  * smoothing with exact tridiagonal solves in each column (Eq. jacobi),
  * horizontal-only 2x2 coarsening, prolongation by natural injection,
  * restriction as its dual, and a few smoothing sweeps instead of a coarse
- * solve (Algorithm 1). The Krylov loop is conjugate gradients (Section 4.1).
+ * solve (Algorithm 1). The Krylov loop is conjugate gradients or BiCGStab
+ * (Section 4.1).
  *
  * Operator. H is a symmetric positive definite face-coupling operator that
  * stands in for the paper's finite-element H (Eq. helmholtz_operator):
@@ -69,7 +70,9 @@ enum {
 };
 
 enum { HELMHOLTZ_FP64 = 0, HELMHOLTZ_FP32 = 1 };               /* V-cycle precision   */
-enum { HELMHOLTZ_CG_STANDARD = 0, HELMHOLTZ_CG_FLEXIBLE = 1 };  /* beta of the CG loop */
+/* Krylov method of helmholtz_solve (Section 4.1): conjugate gradients with the
+ * Fletcher-Reeves (standard) or Polak-Ribiere (flexible) beta, or BiCGStab. */
+enum { HELMHOLTZ_CG_STANDARD = 0, HELMHOLTZ_CG_FLEXIBLE = 1, HELMHOLTZ_BICGSTAB = 2 };
 
 #define HELMHOLTZ_NZ_MAX 120
 #define HELMHOLTZ_WORKSPACE_ALIGN 256
@@ -83,7 +86,7 @@ typedef struct {
     int32_t n_coarse;     /* sweeps on the coarsest level (>= 1)                             */
     double omega;         /* over-relaxation of Eq. jacobi, 0 < omega <= 1.5                 */
     int32_t mg_precision; /* HELMHOLTZ_FP64 or HELMHOLTZ_FP32 (V-cycle arithmetic)           */
-    int32_t cg_variant;   /* HELMHOLTZ_CG_STANDARD or HELMHOLTZ_CG_FLEXIBLE                  */
+    int32_t cg_variant;   /* HELMHOLTZ_CG_STANDARD, _CG_FLEXIBLE or HELMHOLTZ_BICGSTAB       */
     int32_t max_batch;    /* largest batch any call will pass, >= 1                          */
 } helmholtz_config;
 
@@ -116,6 +119,9 @@ int helmholtz_apply(helmholtz_t h, const double* x, double* y, int32_t batch,
 
 /* x = M b: one V-cycle of Algorithm 1 from a zero initial guess, in the
  * handle's mg_precision (float32 V-cycles round b once and widen x once).
+ * This is also the preconditioner-only solver PreOnly(H, M) of Section 4.1:
+ * with nlevels = 1 it is the line relaxation P_H^(Jac)(omega, n_coarse),
+ * n_coarse block-Jacobi sweeps (Eq. jacobi) from x = 0.
  * b and x [batch][nz][ncol] float64, must not overlap. Asynchronous. */
 int helmholtz_vcycle(helmholtz_t h, const double* b, double* x, int32_t batch,
                      helmholtz_stream_t stream);
@@ -125,12 +131,16 @@ int helmholtz_vcycle(helmholtz_t h, const double* b, double* x, int32_t batch,
 int helmholtz_vcycle_f32(helmholtz_t h, const float* b, float* x, int32_t batch,
                          helmholtz_stream_t stream);
 
-/* Solve H x = b by conjugate gradients (Section 4.1) preconditioned by one
- * V-cycle per iteration, from x = 0, independently for each right-hand side.
- * The outer loop (residual update, dot products, norms, solution update) is
- * float64; the V-cycle runs in mg_precision.
+/* Solve H x = b by a Krylov method of Section 4.1 preconditioned by one
+ * V-cycle per preconditioner application, from x = 0, independently for each
+ * right-hand side. cg_variant selects conjugate gradients (one product with H
+ * and one V-cycle per iteration) or right-preconditioned BiCGStab (two of
+ * each per iteration, shadow residual b; a zero inner product before
+ * convergence stops that right-hand side and the call returns
+ * HELMHOLTZ_NOT_CONVERGED). The outer loop (residual update, dot products,
+ * norms, solution update) is float64; the V-cycle runs in mg_precision.
  *   rtol     stop when ||r||_2 <= rtol ||b||_2 (recursively updated residual)
- *   maxiter  largest number of iterations (applications of H), >= 1
+ *   maxiter  largest number of iterations, >= 1
  *   iters    host [batch]: iterations taken per right-hand side (may be NULL)
  *   relres   host [batch]: final ||r||_2 / ||b||_2 (0 when b = 0) (may be NULL)
  * Synchronises `stream` once per iteration for the convergence test.

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhelmholtz.so")
 OK, NOT_CONVERGED = 0, 1
 EINVAL, ESHAPE, EWORKSPACE, ENONFINITE, EHIP = -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
-CG_STANDARD, CG_FLEXIBLE = 0, 1
+CG_STANDARD, CG_FLEXIBLE, BICGSTAB = 0, 1, 2
 NZ_MAX = 120
 WORKSPACE_ALIGN = 256
 

@@ -72,7 +72,8 @@ bool config_ok(const helmholtz_config* c) {
     if (c->n_pre < 0 || c->n_post < 0 || c->n_coarse < 1) return false;
     if (!(c->omega > 0.0 && c->omega <= 1.5)) return false;
     if (c->mg_precision != HELMHOLTZ_FP64 && c->mg_precision != HELMHOLTZ_FP32) return false;
-    if (c->cg_variant != HELMHOLTZ_CG_STANDARD && c->cg_variant != HELMHOLTZ_CG_FLEXIBLE)
+    if (c->cg_variant != HELMHOLTZ_CG_STANDARD && c->cg_variant != HELMHOLTZ_CG_FLEXIBLE &&
+        c->cg_variant != HELMHOLTZ_BICGSTAB)
         return false;
     if (c->max_batch < 1) return false;
     return true;
@@ -102,6 +103,11 @@ struct helmholtz_s {
     double* p = nullptr;
     double* q = nullptr;
     double* z = nullptr;  // float64 preconditioned residual (float64 V-cycle)
+    // BiCGStab only: shadow residual r0, s, t, s_hat (p_hat is z, v is q)
+    double* r0 = nullptr;
+    double* s = nullptr;
+    double* t = nullptr;
+    double* sh = nullptr;
     // r, p, q, z are tiled [B][nvp]; x and b of the ABI are [B][n]
     double* partial = nullptr;
     double* partial2 = nullptr;
@@ -164,13 +170,19 @@ void layout(helmholtz_s* h, Carver& cv) {
     h->p = cv.take<double>(nb);
     h->q = cv.take<double>(nb);
     h->z = cv.take<double>(nb);
+    if (h->cfg.cg_variant == HELMHOLTZ_BICGSTAB) {
+        h->r0 = cv.take<double>(nb);
+        h->s = cv.take<double>(nb);
+        h->t = cv.take<double>(nb);
+        h->sh = cv.take<double>(nb);
+    }
     const int ntile0 = (h->lev[0].ncol + kBlock - 1) / kBlock;
     const int nkc0 = (nz + kApplyChunk - 1) / kApplyChunk;
     const int ntile32 = h->lev[0].ncolp / kTile;
     h->pstride = std::max(std::max(kRedBlocks, ntile0 * nkc0), ntile32);
     h->partial = cv.take<double>(size_t(B) * h->pstride);
     h->partial2 = cv.take<double>(size_t(B) * h->pstride);
-    h->sc = cv.take<double>(size_t(B) * 8);
+    h->sc = cv.take<double>(size_t(B) * kScal);
     h->active = cv.take<int>(size_t(B));
     h->flags = cv.take<int>(4);
 }
@@ -363,19 +375,23 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
 }
 
 template <typename T>
-void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, bool dot,
-                  const int* active, hipStream_t s) {
+void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int dot,
+                  const int* active, hipStream_t s, const T* w = nullptr) {
     const Level& v = h->lev[l];
     const int ntile = (v.ncol + kBlock - 1) / kBlock;
     const int nkc = (h->nz + kApplyChunk - 1) / kApplyChunk;
     const dim3 grid(ntile * nkc * batch);
     const bool prof = (l == 0 && sizeof(T) == 8) && prof_begin(h, HELMHOLTZ_PROF_APPLY_FINE, s);
-    if (dot)
-        hipLaunchKernelGGL((k_apply<T, true, kApplyChunk>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), x, y, batch, nkc, cg_state(h), active);
-    else
-        hipLaunchKernelGGL((k_apply<T, false, kApplyChunk>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), x, y, batch, nkc, cg_state(h), active);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), x, y, w, batch, nkc,
+                           cg_state(h), active);
+    };
+    switch (dot) {
+        case kDotXY: go(k_apply<T, kDotXY, kApplyChunk>); break;
+        case kDotWY: go(k_apply<T, kDotWY, kApplyChunk>); break;
+        case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk>); break;
+        default: go(k_apply<T, kDotNone, kApplyChunk>); break;
+    }
     if (prof)  // x, kh[2], kv, delta read; y written
         prof_end(h, HELMHOLTZ_PROF_APPLY_FINE, 6.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
 }
@@ -505,6 +521,82 @@ int wait_published(helmholtz_s* h, hipStream_t s, const std::vector<int>& need, 
     }
 }
 
+// out = M u for float64 tiled vectors (float32 V-cycles convert on the way in
+// and out through the level-0 float32 buffers).
+int precondition_into(helmholtz_s* h, const double* u, double* out, int batch, const int* active,
+                      hipStream_t s) {
+    if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
+        vcycle_level<double>(h, 0, u, out, batch, active, s);
+    } else {
+        LevelData<float>& f = h->lev[0].f;
+        const int64_t n = int64_t(batch) * h->nvp;
+        convert<double, float>(u, f.b, n, s);
+        vcycle_level<float>(h, 0, f.b, f.x, batch, active, s);
+        convert<float, double>(f.x, out, n, s);
+    }
+    return last_error();
+}
+
+// Right-preconditioned BiCGStab (Section 4.1) after the shared start
+// (x = 0, r = r0 = b, rho = ||b||^2 published). Per iteration two products
+// with H and two V-cycles; the inner products (r0, v), (t, s) with (t, t),
+// and (r0, r) with ||r||^2 are the four global sums of Section 3.7. it/rel
+// are updated for every right-hand side that was active in an iteration.
+int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
+                  const std::vector<double>& bnorm2, std::vector<int32_t>& it,
+                  std::vector<double>& rel, hipStream_t s) {
+    const Level& v0 = h->lev[0];
+    const int64_t n = h->nvp;
+    const int ntile32 = v0.ncolp / kTile;
+    const int ntile0 = (v0.ncol + kBlock - 1) / kBlock;
+    const int nkc0 = (h->nz + kApplyChunk - 1) / kApplyChunk;
+    const dim3 red(kRedBlocks * batch), blk(kBlock), fin(kFinBlock), tgrid(ntile32 * batch);
+    const CgState st = cg_state(h);
+    std::vector<int> was_active(batch);
+    bool broke = false;
+    for (int iter = 1;; ++iter) {
+        for (int i = 0; i < batch; ++i) was_active[i] = h->hact[i];
+        // p = r + beta (p - omega v); p_hat = M p; v = H p_hat; alpha = rho / (r0, v)
+        hipLaunchKernelGGL(k_bicg_p, red, blk, 0, s, h->r, h->q, h->p, n, kRedBlocks, h->sc,
+                           h->active, iter == 1 ? 1 : 0);
+        if (int e = precondition_into(h, h->p, h->z, batch, h->active, s)) return e;
+        launch_apply<double>(h, 0, h->z, h->q, batch, kDotWY, h->active, s, h->r0);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBiAlpha),
+                           ntile0 * nkc0, 0);
+        // s = r - alpha v; s_hat = M s; t = H s_hat; omega = (t, s) / (t, t)
+        hipLaunchKernelGGL(k_bicg_s, red, blk, 0, s, h->r, h->q, h->s, n, kRedBlocks, h->sc,
+                           h->active);
+        if (int e = precondition_into(h, h->s, h->sh, batch, h->active, s)) return e;
+        launch_apply<double>(h, 0, h->sh, h->t, batch, kDotWYYY, h->active, s, h->s);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBiOmega),
+                           ntile0 * nkc0, 0);
+        // x += alpha p_hat + omega s_hat; r = s - omega t; (r0, r), ||r||^2, published
+        hipLaunchKernelGGL(k_bicg_xr, tgrid, blk, 0, s, x, h->r, h->z, h->sh, h->s, h->t, h->r0,
+                           v0.ncol, h->nz, v0.nvp, st);
+        hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBiRR), ntile32, iter);
+        if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
+        if (int e = wait_published(h, s, was_active, iter)) return e;
+        bool still = false;
+        for (int i = 0; i < batch; ++i) {
+            if (!was_active[i]) continue;
+            it[i] = iter;
+            const double rr = h->hsc[i * kScal + kRR];
+            if (!std::isfinite(rr)) return HELMHOLTZ_ENONFINITE;
+            rel[i] = std::sqrt(rr / bnorm2[i]);
+            broke = broke || h->hsc[i * kScal + kBreak] != 0.0;
+            still = still || h->hact[i];
+        }
+        if (!still) break;
+        if (iter >= maxiter) {
+            broke = true;
+            break;
+        }
+    }
+    // the caller may read x as soon as this returns on the host
+    HH_CHECK(hipStreamSynchronize(s));
+    return broke ? HELMHOLTZ_NOT_CONVERGED : HELMHOLTZ_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -569,12 +661,12 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
     };
     // host-coherent pinned memory: the device publishes the CG scalars here
     if (hipHostMalloc(reinterpret_cast<void**>(&h->hsc),
-                      size_t(h->B) * 8 * sizeof(double) + size_t(h->B) * 2 * sizeof(int) + 16,
+                      size_t(h->B) * kScal * sizeof(double) + size_t(h->B) * 2 * sizeof(int) + 16,
                       hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
         h->hsc = nullptr;
         return fail(HELMHOLTZ_EHIP);
     }
-    h->hact = reinterpret_cast<int*>(h->hsc + size_t(h->B) * 8);
+    h->hact = reinterpret_cast<int*>(h->hsc + size_t(h->B) * kScal);
     h->hseq = h->hact + h->B;
     h->hflags = h->hseq + h->B;
     for (int i = 0; i < h->B; ++i) h->hseq[i] = -1;
@@ -695,7 +787,7 @@ int helmholtz_apply(helmholtz_t h, const double* x, double* y, int32_t batch,
     if (!x || !y) return HELMHOLTZ_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     retile<double, double, true>(h, x, h->p, batch, s);
-    launch_apply<double>(h, 0, h->p, h->q, batch, false, nullptr, s);
+    launch_apply<double>(h, 0, h->p, h->q, batch, kDotNone, nullptr, s);
     retile<double, double, false>(h, h->q, y, batch, s);
     return last_error();
 }
@@ -741,21 +833,23 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     const dim3 tgrid(ntile32 * batch);
     const bool mixed = h->cfg.mg_precision == HELMHOLTZ_FP32;
     const bool flex = h->cfg.cg_variant == HELMHOLTZ_CG_FLEXIBLE;
-    float* r32 = mixed ? h->lev[0].f.b : nullptr;
+    const bool bicg = h->cfg.cg_variant == HELMHOLTZ_BICGSTAB;
+    float* r32 = mixed && !bicg ? h->lev[0].f.b : nullptr;
     float* z32 = mixed ? h->lev[0].f.x : nullptr;
     const dim3 red(kRedBlocks * batch), blk(kBlock), fin(kFinBlock);
     const CgState st = cg_state(h);
 
     // the host mirror doubles as staging for the initial scalars
     for (int i = 0; i < batch; ++i) {
-        for (int j = 0; j < 8; ++j) h->hsc[i * 8 + j] = 0.0;
-        h->hsc[i * 8 + kRtol2] = rtol * rtol;
+        for (int j = 0; j < kScal; ++j) h->hsc[i * kScal + j] = 0.0;
+        h->hsc[i * kScal + kRtol2] = rtol * rtol;
         __atomic_store_n(&h->hseq[i], -1, __ATOMIC_RELEASE);
     }
-    HH_CHECK(hipMemcpyAsync(h->sc, h->hsc, size_t(batch) * 8 * sizeof(double),
+    HH_CHECK(hipMemcpyAsync(h->sc, h->hsc, size_t(batch) * kScal * sizeof(double),
                             hipMemcpyHostToDevice, s));
     // x = 0, r = b, ||b||^2
-    hipLaunchKernelGGL(k_cg_init, tgrid, blk, 0, s, b, x, h->r, r32, v0.ncol, h->nz, v0.nvp, st);
+    hipLaunchKernelGGL(k_cg_init, tgrid, blk, 0, s, b, x, h->r, r32, bicg ? h->r0 : nullptr,
+                       v0.ncol, h->nz, v0.nvp, st);
     hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBB), ntile32, 0);
     if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
     std::vector<int> need(batch, 1);
@@ -765,7 +859,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     std::vector<double> rel(batch, 0.0);
     bool any = false;
     for (int i = 0; i < batch; ++i) {
-        bnorm2[i] = h->hsc[i * 8 + kBB];
+        bnorm2[i] = h->hsc[i * kScal + kBB];
         if (!std::isfinite(bnorm2[i])) return HELMHOLTZ_ENONFINITE;
         any = any || h->hact[i];
         rel[i] = h->hact[i] ? 1.0 : 0.0;
@@ -778,6 +872,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         return status;
     };
     if (!any) return finish(HELMHOLTZ_OK);
+    if (bicg) return finish(bicgstab_loop(h, x, batch, maxiter, bnorm2, it, rel, s));
 
     // z = M r, rho = r.z, p = z
     if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
@@ -802,7 +897,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     for (int iter = 1;; ++iter) {
         for (int i = 0; i < batch; ++i) was_active[i] = h->hact[i];
         // q = H p, alpha = rho / p.q
-        launch_apply<double>(h, 0, h->p, h->q, batch, true, h->active, s);
+        launch_apply<double>(h, 0, h->p, h->q, batch, kDotXY, h->active, s);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
                            0);
         // x += alpha p, r -= alpha q, ||r||^2 and the convergence flags, published
@@ -815,7 +910,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         for (int i = 0; i < batch; ++i) {
             if (!was_active[i]) continue;
             it[i] = iter;
-            const double rr = h->hsc[i * 8 + kRR];
+            const double rr = h->hsc[i * kScal + kRR];
             if (!std::isfinite(rr)) return finish(HELMHOLTZ_ENONFINITE);
             rel[i] = std::sqrt(rr / bnorm2[i]);
             still = still || h->hact[i];

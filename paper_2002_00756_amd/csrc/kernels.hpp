@@ -366,10 +366,15 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
     return s;
 }
 
-// Per right-hand-side scalars sc[rhs*8 + ...]:
-enum { kBB = 0, kRho = 1, kPQ = 2, kAlpha = 3, kRR = 4, kBeta = 5, kZQ = 6, kRtol2 = 7 };
+// Per right-hand-side scalars sc[rhs*kScal + ...] (kBreak: 1 after a
+// BiCGStab breakdown):
+enum { kBB = 0, kRho = 1, kPQ = 2, kAlpha = 3, kRR = 4, kBeta = 5, kZQ = 6, kRtol2 = 7,
+       kOmega = 8, kBreak = 9, kScal = 12 };
+// CG: BB, then per iteration Rho/Alpha/RR/Beta(Flex). BiCGStab: BB, then per
+// iteration BiAlpha (rho / (r0, v)), BiOmega ((t, s) / (t, t)) and BiRR
+// ((r0, r), ||r||^2, convergence test, beta for the next step).
 enum FinalizeMode { kFinBB = 0, kFinRho = 1, kFinAlpha = 2, kFinRR = 3, kFinBeta = 4,
-                    kFinBetaFlex = 5 };
+                    kFinBetaFlex = 5, kFinBiAlpha = 6, kFinBiOmega = 7, kFinBiRR = 8 };
 
 // Reduction state shared by the Krylov kernels. hsc/hact/hseq live in pinned,
 // host-coherent memory: the finalisation of the norm reductions publishes the
@@ -421,27 +426,33 @@ __device__ __forceinline__ void store_partial(const CgState& st, int rhs, int bl
 }
 
 // One block per right-hand side: add the `cnt` partials in a fixed order and
-// derive the CG scalar. The norm reductions (kFinBB, kFinRR) also publish the
-// scalars and flags to the host mirror, then the sequence number `seq`.
+// derive the Krylov scalar. The norm reductions (kFinBB, kFinRR, kFinBiRR)
+// also publish the scalars and flags to the host mirror, then the sequence
+// number `seq`; they publish even for a right-hand side that is no longer
+// active (its values unchanged), so the host never waits in vain.
 constexpr int kFinBlock = 1024;  // threads of the finalisation block
 
 __global__ void __launch_bounds__(kFinBlock)
 k_finalize(CgState st, int mode, int cnt, int seq) {
     __shared__ double sh[kFinBlock / 64];
     const int rhs = blockIdx.x;
-    if (mode != kFinBB && !st.active[rhs]) return;
-    const bool two = mode == kFinBetaFlex;
-    const double t1 = reduce_partials(st.partial + int64_t(rhs) * st.pstride, cnt, sh);
-    const double t2 = two ? reduce_partials(st.partial2 + int64_t(rhs) * st.pstride, cnt, sh) : 0.0;
+    const bool publish = mode == kFinBB || mode == kFinRR || mode == kFinBiRR;
+    const bool live = mode == kFinBB || st.active[rhs] != 0;
+    if (!live && !publish) return;
+    const bool two = mode == kFinBetaFlex || mode == kFinBiOmega || mode == kFinBiRR;
+    double t1 = 0.0, t2 = 0.0;
+    if (live) {
+        t1 = reduce_partials(st.partial + int64_t(rhs) * st.pstride, cnt, sh);
+        if (two) t2 = reduce_partials(st.partial2 + int64_t(rhs) * st.pstride, cnt, sh);
+    }
     if (threadIdx.x != 0) return;
-    double* v = st.sc + rhs * 8;
-    bool publish = false;
-    switch (mode) {
+    double* v = st.sc + rhs * kScal;
+    switch (live ? mode : -1) {
         case kFinBB:
             v[kBB] = t1;
             v[kRR] = t1;
+            v[kRho] = t1;  // BiCGStab: (r0, r) with r0 = r = b
             st.active[rhs] = (t1 > 0.0) ? 1 : 0;
-            publish = true;
             break;
         case kFinRho:
             v[kRho] = t1;
@@ -453,7 +464,6 @@ k_finalize(CgState st, int mode, int cnt, int seq) {
         case kFinRR:
             v[kRR] = t1;
             if (t1 <= v[kRtol2] * v[kBB]) st.active[rhs] = 0;
-            publish = true;
             break;
         case kFinBeta:
             v[kBeta] = t1 / v[kRho];
@@ -465,19 +475,48 @@ k_finalize(CgState st, int mode, int cnt, int seq) {
             v[kZQ] = t2;
             v[kRho] = t1;
             break;
+        case kFinBiAlpha:  // t1 = (r0, v)
+            if (t1 == 0.0) {
+                v[kBreak] = 1.0;
+                st.active[rhs] = 0;
+            } else {
+                v[kAlpha] = v[kRho] / t1;
+            }
+            break;
+        case kFinBiOmega:  // t1 = (t, s), t2 = (t, t); t = 0 only if s = 0
+            v[kOmega] = t2 > 0.0 ? t1 / t2 : 0.0;
+            break;
+        case kFinBiRR:  // t1 = (r0, r), t2 = ||r||^2
+            v[kRR] = t2;
+            if (t2 <= v[kRtol2] * v[kBB]) {
+                st.active[rhs] = 0;
+            } else if (t1 == 0.0 || v[kOmega] == 0.0) {
+                v[kBreak] = 1.0;
+                st.active[rhs] = 0;
+            } else {
+                v[kBeta] = (t1 / v[kRho]) * (v[kAlpha] / v[kOmega]);
+                v[kRho] = t1;
+            }
+            break;
+        default:
+            break;
     }
     if (publish) {
-        for (int i = 0; i < 8; ++i) st.hsc[rhs * 8 + i] = v[i];
+        for (int i = 0; i < kScal; ++i) st.hsc[rhs * kScal + i] = v[i];
         st.hact[rhs] = st.active[rhs];
         __threadfence_system();
         __hip_atomic_store(&st.hseq[rhs], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
-template <typename T, bool DOT, int KC>
+// DOT: 0 none; kDotXY x . y (CG: p . q); kDotWY w . y (BiCGStab: (r0, v));
+// kDotWYYY w . y and y . y (BiCGStab: (t, s), (t, t)). Partial sums per block.
+enum { kDotNone = 0, kDotXY = 1, kDotWY = 2, kDotWYYY = 3 };
+
+template <typename T, int DOT, int KC>
 __global__ void __launch_bounds__(kBlock)
-k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, int nkc,
-        CgState st, const int* __restrict__ active) {
+k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
+        int batch, int nkc, CgState st, const int* __restrict__ active) {
     __shared__ double sh[kBlock / 64];
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int rhs = lb % batch, rest = lb / batch;
@@ -489,8 +528,9 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
     const int64_t nv = L.nvp;
     x += rhs * nv;
     y += rhs * nv;
+    if (DOT >= kDotWY) w += rhs * nv;
     const T* khN = L.kh + nv;
-    double acc = 0.0;
+    double acc = 0.0, acc2 = 0.0;
     if (valid) {
         int nb[4];
 #pragma unroll
@@ -538,14 +578,20 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, int batch, i
                 v += kvv[j + 1] * (xo - xc[j + 2]);
                 v += kvv[j] * (xo - xc[j]);
                 y[ob + kTile * k] = v;
-                if (DOT) acc += double(xo) * double(v);
+                if (DOT == kDotXY) acc += double(xo) * double(v);
+                if (DOT >= kDotWY) acc += double(w[ob + kTile * k]) * double(v);
+                if (DOT == kDotWYYY) acc2 += double(v) * double(v);
             }
         }
     }
-    if (DOT) {
-        // p . q over the right-hand side's blocks, then alpha = rho / p.q
+    if (DOT != kDotNone) {
         const double s = block_sum(acc, sh);
-        store_partial(st, rhs, rest, s, 0.0, false);
+        double s2 = 0.0;
+        if (DOT == kDotWYYY) {
+            __syncthreads();
+            s2 = block_sum(acc2, sh);
+        }
+        store_partial(st, rhs, rest, s, s2, DOT == kDotWYYY);
     }
 }
 
@@ -850,11 +896,12 @@ __device__ __forceinline__ TileGrid tile_grid(int ncol) {
 }
 constexpr int kTileGroups = kBlock / kTile;
 
-// x = 0, r = b, r32 = float(b) (b and x in the ABI layout); partial ||b||^2
-// per tile.
+// x = 0, r = b, r32 = float(b), r0 = b (b and x in the ABI layout; r32 and
+// r0 may be null); partial ||b||^2 per tile.
 __global__ void __launch_bounds__(kBlock)
 k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
-          float* __restrict__ r32, int ncol, int nz, int nvp, CgState st) {
+          float* __restrict__ r32, double* __restrict__ r0, int ncol, int nz, int nvp,
+          CgState st) {
     __shared__ double sh[kBlock / 64];
     const TileGrid t = tile_grid(ncol);
     const int64_t n = int64_t(nz) * ncol;
@@ -866,6 +913,7 @@ k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restri
             x[ia + int64_t(k) * ncol] = 0.0;
             r[it + kTile * k] = v;
             if (r32) r32[it + kTile * k] = float(v);
+            if (r0) r0[it + kTile * k] = v;
             acc += v * v;
         }
     }
@@ -882,7 +930,7 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ 
     __shared__ double sh[kBlock / 64];
     const TileGrid t = tile_grid(ncol);
     if (!st.active[t.rhs]) return;
-    const double alpha = st.sc[t.rhs * 8 + kAlpha];
+    const double alpha = st.sc[t.rhs * kScal + kAlpha];
     const int64_t n = int64_t(nz) * ncol;
     double acc = 0.0;
     if (t.valid) {
@@ -950,7 +998,7 @@ k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
            const double* __restrict__ sc, const int* __restrict__ active, int init) {
     const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
     if (!active[rhs]) return;
-    const double beta = init ? 0.0 : sc[rhs * 8 + kBeta];
+    const double beta = init ? 0.0 : sc[rhs * kScal + kBeta];
     int64_t i0, i1;
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
@@ -959,6 +1007,71 @@ k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
         const double zv = double(z[off + i]);
         p[off + i] = init ? zv : zv + beta * p[off + i];
     }
+}
+
+// ---------------------------------------------------------------------------
+// BiCGStab vector steps (tiled vectors; x in the ABI layout).
+
+// p = r + beta (p - omega v)   (init: p = r)
+__global__ void __launch_bounds__(kBlock)
+k_bicg_p(const double* __restrict__ r, const double* __restrict__ v, double* __restrict__ p,
+         int64_t n, int nblk, const double* __restrict__ sc, const int* __restrict__ active,
+         int init) {
+    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    if (!active[rhs]) return;
+    const double beta = init ? 0.0 : sc[rhs * kScal + kBeta];
+    const double omega = init ? 0.0 : sc[rhs * kScal + kOmega];
+    int64_t i0, i1;
+    grid_range(n, nblk, blk, i0, i1);
+    const int64_t off = int64_t(rhs) * n;
+#pragma unroll 4
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock)
+        p[off + i] = init ? r[off + i] : r[off + i] + beta * (p[off + i] - omega * v[off + i]);
+}
+
+// s = r - alpha v
+__global__ void __launch_bounds__(kBlock)
+k_bicg_s(const double* __restrict__ r, const double* __restrict__ v, double* __restrict__ s,
+         int64_t n, int nblk, const double* __restrict__ sc, const int* __restrict__ active) {
+    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    if (!active[rhs]) return;
+    const double alpha = sc[rhs * kScal + kAlpha];
+    int64_t i0, i1;
+    grid_range(n, nblk, blk, i0, i1);
+    const int64_t off = int64_t(rhs) * n;
+#pragma unroll 4
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) s[off + i] = r[off + i] - alpha * v[off + i];
+}
+
+// x += alpha p_hat + omega s_hat (x in the ABI layout); r = s - omega t;
+// partials (r0, r) and ||r||^2 per tile.
+__global__ void __launch_bounds__(kBlock)
+k_bicg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restrict__ ph,
+          const double* __restrict__ shat, const double* __restrict__ s,
+          const double* __restrict__ t, const double* __restrict__ r0, int ncol, int nz, int nvp,
+          CgState st) {
+    __shared__ double sh[kBlock / 64];
+    const TileGrid g = tile_grid(ncol);
+    if (!st.active[g.rhs]) return;
+    const double alpha = st.sc[g.rhs * kScal + kAlpha];
+    const double omega = st.sc[g.rhs * kScal + kOmega];
+    const int64_t n = int64_t(nz) * ncol;
+    double a1 = 0.0, a2 = 0.0;
+    if (g.valid) {
+        const int64_t ia = g.rhs * n + g.c, it = g.rhs * int64_t(nvp) + tile_base(g.c, nz);
+        for (int k = g.g; k < nz; k += kTileGroups) {
+            const int64_t o = it + kTile * k;
+            x[ia + int64_t(k) * ncol] += alpha * ph[o] + omega * shat[o];
+            const double v = s[o] - omega * t[o];
+            r[o] = v;
+            a1 += r0[o] * v;
+            a2 += v * v;
+        }
+    }
+    const double s1 = block_sum(a1, sh);
+    __syncthreads();
+    const double s2 = block_sum(a2, sh);
+    store_partial(st, g.rhs, g.tile, s1, s2, true);
 }
 
 // ---------------------------------------------------------------------------

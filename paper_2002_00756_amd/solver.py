@@ -53,9 +53,22 @@ class Operator:
 
     Parameters follow P_H^(MG)(L, omega, n_pre, n_post) with n_coarse sweeps on
     the coarsest level. ``precision`` is the V-cycle arithmetic ("fp64" or
-    "fp32"); the Krylov loop is always float64. ``cg`` selects the beta of the
-    conjugate-gradient update ("standard" or "flexible").
+    "fp32"); the Krylov loop is always float64. ``cg`` selects the Krylov
+    method of ``solve``: conjugate gradients with the standard or flexible beta
+    ("standard", "flexible"), or right-preconditioned BiCGStab ("bicgstab",
+    where ``iters`` counts iterations of two products with H each). With
+    ``nlevels=1`` the preconditioner is P_H^(Jac)(omega, n_coarse), and
+    ``vcycle`` alone is the preconditioner-only solver PreOnly.
     """
+
+    _KRYLOV = {"standard": _lib.CG_STANDARD, "flexible": _lib.CG_FLEXIBLE,
+               "bicgstab": _lib.BICGSTAB}
+
+    @classmethod
+    def _krylov(cls, cg):
+        if cg not in cls._KRYLOV:
+            raise ValueError(f"cg must be one of {sorted(cls._KRYLOV)}, not {cg!r}")
+        return cls._KRYLOV[cg]
 
     def __init__(self, N, nz, kh, kv, delta, nlevels, n_pre=2, n_post=2, n_coarse=4,
                  omega=0.8, precision="fp64", cg="standard", max_batch=1, device="cuda"):
@@ -68,9 +81,10 @@ class Operator:
         self.precision = precision
         self.cfg = _lib.Config(self.N, self.nz, self.nlevels, n_pre, n_post, n_coarse,
                                float(omega), _lib.FP32 if precision == "fp32" else _lib.FP64,
-                               _lib.CG_FLEXIBLE if cg == "flexible" else _lib.CG_STANDARD,
+                               self._krylov(cg),
                                int(max_batch))
         self.max_batch = int(max_batch)
+        self.cg = cg
         nbytes = self.lib.helmholtz_workspace_bytes(ctypes.byref(self.cfg))
         if nbytes == 0:
             raise _lib.HelmholtzError(_lib.EINVAL if self.N % (1 << (self.nlevels - 1)) == 0
@@ -142,7 +156,8 @@ class Operator:
         return x[0] if sq else x
 
     def solve(self, b, rtol=1e-8, maxiter=200, out=None) -> SolveResult:
-        """MG-preconditioned CG from x = 0; returns the solution and per-RHS statistics."""
+        """Preconditioned Krylov solve (the handle's ``cg`` method) from x = 0; returns
+        the solution and per-RHS statistics."""
         b, sq = self._vec(b)
         x = torch.empty_like(b) if out is None else out.view(b.shape)
         nb = b.shape[0]
