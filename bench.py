@@ -72,6 +72,19 @@ def cg_bytes_per_unknown(vc_words, mixed, flexible):
     return apply_dot + update + vc + dot + pupd
 
 
+def bicgstab_bytes_per_unknown(vc_words, mixed):
+    """Algorithmic bytes per unknown of one BiCGStab iteration (outer loop in
+    float64): two preconditioner applications (float32 ones convert their
+    input and output), two applies with a fused inner product, and the p, s
+    and x/r updates."""
+    precond = vc_words * (4 if mixed else 8) + (2 * (8 + 4) if mixed else 0)
+    apply_dot = 6 * 8 + 8              # p_hat or s_hat, kh[2], kv, delta, dot partner; out
+    p_upd = 3 * 8 + 8                  # r, v, p read; p written
+    s_upd = 2 * 8 + 8                  # r, v read; s written
+    xr_upd = 2 * 8 + 5 * 8 + 8         # x read+written; p_hat, s_hat, s, t, r0 read; r written
+    return 2 * (precond + apply_dot) + p_upd + s_upd + xr_upd
+
+
 def kernel_sources_hash():
     h = hashlib.sha256()
     for f in ("kernels.hpp", "helmholtz.hip"):
@@ -171,6 +184,75 @@ def batch_leg(Operator, torch, dev, steps=2, warmup=1):
     }
 
 
+def solver_comparison(Operator, torch, dev, reps=5):
+    """Pressure-solver configurations of the paper's Section 5.1 (Table 1) and
+    the timestep-robustness study of Section 5.3 (Table 5), on the benchmark
+    workload with the synthetic operator, float32 preconditioners inside
+    float64 Krylov loops. Each entry: time per pressure solve (wall clock
+    around the call, b and x in HBM), iterations (Krylov solvers), the true
+    float64 relative residual reached, and GB/s of the byte model.
+
+    Configurations: line relaxation = PreOnly with P_Jac(0.8, 10); Krylov(eps)
+    = BiCGStab with P_Jac(1, 1); MG(L) = PreOnly with P_MG(L, 0.8, 2, 2), L =
+    1..4; Krylov-MG(eps, 4) = BiCGStab with P_MG(4, 0.8, 2, 2); eps in {1e-2,
+    1e-3, 1e-6}. Robustness: w_h = CFL_h^2 / 4 (the horizontal coupling
+    relative to the mean of delta, which is 1) for CFL_h = 4, 6, 8, with
+    MG(3), Kr2 = Krylov(1e-2) and Kr6 = Krylov(1e-6)."""
+    w = workloads.C192x70
+    n = w.n
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3, r
+
+    def run(coeffs, b, configs):
+        bn = torch.linalg.norm(b)
+        rows = []
+        for name, L, prm, eps in configs:
+            op = Operator(w.N, w.nz, *coeffs, L, *prm, precision="fp32",
+                          cg="bicgstab" if eps else "standard", device=dev)
+            if eps:
+                ms, res = timed(lambda: op.solve(b, rtol=eps, maxiter=2000))
+                x, iters = res.x, res.iters[0]
+                gbs = bicgstab_bytes_per_unknown(vcycle_words(L, *prm[:3]), True) * iters * n
+            else:
+                ms, x = timed(lambda: op.vcycle(b))
+                iters = None
+                gbs = (vcycle_words(L, *prm[:3]) + 4.0) * 4 * n   # + layout conversion
+            true = float(torch.linalg.norm(b - op.apply(x)) / bn)
+            rows.append({"name": name, "ms": ms, "iters": iters, "relres": true,
+                         "GBps": gbs / (ms * 1e-3) / 1e9})
+            del op
+        return rows
+
+    MG = (2, 2, 4, 0.8)
+    kh, kv, delta = workloads.workload_coefficients(w)
+    coeffs = tuple(torch.from_numpy(a).to(dev) for a in (kh, kv, delta))
+    b = torch.from_numpy(workloads.rhs(w.N, w.nz)[0]).to(dev)
+    configs = [("line relaxation", 1, (2, 2, 10, 0.8), None)]
+    configs += [(f"Krylov({e:g})", 1, (2, 2, 1, 1.0), e) for e in (1e-2, 1e-3, 1e-6)]
+    configs += [(f"MG({L})", L, MG, None) for L in (1, 2, 3, 4)]
+    configs += [(f"Krylov-MG({e:g},4)", 4, MG, e) for e in (1e-2, 1e-3, 1e-6)]
+    table1 = run(coeffs, b, configs)
+    del coeffs
+    robust = []
+    for cfl in (4, 6, 8):
+        w_h = cfl * cfl / 4.0
+        c = workloads.coefficients(w.N, w.nz, w_h, w.w_v, w.graded)
+        coeffs = tuple(torch.from_numpy(a).to(dev) for a in c)
+        rows = run(coeffs, b, [("MG(3)", 3, MG, None), ("Kr2", 1, (2, 2, 1, 1.0), 1e-2),
+                               ("Kr6", 1, (2, 2, 1, 1.0), 1e-6)])
+        robust.append({"CFL_h": cfl, "w_h": w_h, "solvers": rows})
+        del coeffs
+    return {"workload": f"{w.name} ({w.n} unknowns), float32 preconditioners, float64 Krylov",
+            "table1": table1, "cfl_robustness": robust}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,6 +264,9 @@ def main():
     ap.add_argument("--no-batch-leg", action="store_true",
                     help="skip the C384x70 batch-of-4 forward+adjoint measurement")
     ap.add_argument("--cg", default="standard", choices=["standard", "flexible"])
+    ap.add_argument("--no-solver-comparison", action="store_true",
+                    help="skip the pressure-solver configurations of Section 5.1 and the "
+                         "CFL robustness study")
     ap.add_argument("--probe", action="store_true",
                     help="for counter runs: a few solves plus a 1 GiB device copy of known "
                          "size, no JSON")
@@ -373,6 +458,8 @@ def main():
         del op32, op64, kh_d, kv_d, dl_d
         torch.cuda.empty_cache()
         out["batch4_C384x70"] = batch_leg(Operator, torch, dev)
+    if not args.no_solver_comparison and args.workload == "C192x70":
+        out["solver_comparison"] = solver_comparison(Operator, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, kh, kv, delta, b_np, int(round(it64)))
     print(json.dumps(out), flush=True)

@@ -113,3 +113,14 @@ def test_bench_byte_model():
     # one CG iteration: apply+dot 48, update 52 (mixed) / 48, dot 12 / 16, p-update 20 / 24
     assert bench.cg_bytes_per_unknown(0.0, True, False) == 48 + 52 + 12 + 20
     assert bench.cg_bytes_per_unknown(0.0, False, False) == 48 + 48 + 16 + 24
+
+
+def test_bench_bicgstab_byte_model():
+    """BiCGStab iteration bytes, counted by hand: per preconditioner application
+    a float32 V-cycle of w words (4w bytes) plus its two conversions (12 B
+    each way), per apply 48 B plus the 8 B dot partner; updates p 32, s 24,
+    x/r 64."""
+    import bench
+    w = 41.0
+    assert bench.bicgstab_bytes_per_unknown(w, True) == 2 * (4 * w + 24 + 56) + 32 + 24 + 64
+    assert bench.bicgstab_bytes_per_unknown(w, False) == 2 * (8 * w + 56) + 32 + 24 + 64
