@@ -30,3 +30,12 @@ def face_gradients(level, lam, x):
     g_kv = -((lam[:, :-1] - lam[:, 1:]) * (x[:, :-1] - x[:, 1:])).sum(axis=0)
     g_delta = -(lam * x).sum(axis=0)
     return g_kh, g_kv, g_delta
+
+
+def kv2_gradient(lam, x):
+    """``g_kv2[nz-2][ncol]``: gradient of L with respect to the next-to-nearest
+    vertical couplings of the 9-cell stencil (faces k | k+2), summed over the
+    batch, by the same flux-form rule."""
+    lam = lam.reshape((-1,) + lam.shape[-2:])
+    x = x.reshape((-1,) + x.shape[-2:])
+    return -((lam[:, :-2] - lam[:, 2:]) * (x[:, :-2] - x[:, 2:])).sum(axis=0)

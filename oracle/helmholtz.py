@@ -17,6 +17,16 @@ vertical face (the role of D_1^z + D_2^z), in flux form
 With positive couplings and delta > 0 this is symmetric positive definite
 (a graph Laplacian plus a positive diagonal).
 
+Section 3.5 notes that the paper's H also couples each cell to the cells two
+levels above and below (a 9-cell stencil, H_z pentadiagonal). With the
+optional next-to-nearest coupling K_v2[k,c] between levels k and k+2 the
+operator gains
+
+             + K_v2[k,c]   (x[k,c] - x[k+2,c])   if k < nz-2
+             + K_v2[k-2,c] (x[k,c] - x[k-2,c])   if k > 1,
+
+and the smoother's matrix drops those off-diagonal entries (Section 3.6).
+
 Coarse levels are built by re-discretisation, not by the Galerkin product
 (Section 3.6). Eq. DH_ratios gives how each part scales with the grid: H_0 with
 the cell volume (so the four children's delta add up), the vertical part with
@@ -39,8 +49,9 @@ def face_coeffs(kh: np.ndarray, ftab: np.ndarray) -> np.ndarray:
     return np.stack([flat[:, ftab[d]] for d in range(4)])   # [4][nz][ncol]
 
 
-def apply(level, kh, kv, delta, x):
-    """y = H x on one level, in flux form. ``x`` is ``[..., nz, ncol]``."""
+def apply(level, kh, kv, delta, x, kv2=None):
+    """y = H x on one level, in flux form. ``x`` is ``[..., nz, ncol]``;
+    ``kv2`` (``[nz-2][ncol]``) adds the next-to-nearest vertical couplings."""
     K = face_coeffs(kh, level.ftab)
     y = delta * x
     for d in range(4):
@@ -50,10 +61,14 @@ def apply(level, kh, kv, delta, x):
         flux = kv * dz
         y[..., :-1, :] += flux
         y[..., 1:, :] -= flux
+    if kv2 is not None and x.shape[-2] > 2:
+        flux2 = kv2 * (x[..., :-2, :] - x[..., 2:, :])
+        y[..., :-2, :] += flux2
+        y[..., 2:, :] -= flux2
     return y
 
 
-def assemble(level, kh, kv, delta) -> sp.csr_matrix:
+def assemble(level, kh, kv, delta, kv2=None) -> sp.csr_matrix:
     """Sparse matrix of H, unknown index k*ncol + c (used by the pins)."""
     nz, ncol = delta.shape
     n = nz * ncol
@@ -70,18 +85,22 @@ def assemble(level, kh, kv, delta) -> sp.csr_matrix:
         couple(idx.ravel(), idx[:, level.nbr[d]].ravel(), kh[slot].ravel())
     if nz > 1:
         couple(idx[:-1].ravel(), idx[1:].ravel(), kv.ravel())
+    if kv2 is not None and nz > 2:
+        couple(idx[:-2].ravel(), idx[2:].ravel(), kv2.ravel())
     A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                       shape=(n, n))
     return A.tocsr()
 
 
-def column_tridiagonal(level, kh, kv, delta):
-    """The column operator H_z (Section 3.5) as ``(sub, diag, sup)``, each ``[nz][ncol]``.
+def column_tridiagonal(level, kh, kv, delta, kv2=None):
+    """The smoother's column matrix (Sections 3.5-3.6) as ``(sub, diag, sup)``,
+    each ``[nz][ncol]``.
 
     H_z keeps every coupling inside a column and the whole diagonal of H; the
-    horizontal off-diagonal couplings form the rest, H - H_z. For this 7-point
-    operator H_z is already tridiagonal, so the smoother's matrix (H_z with the
-    next-to-nearest vertical couplings dropped) is H_z itself.
+    horizontal off-diagonal couplings form the rest, H - H_z. The smoother's
+    matrix is H_z with the next-to-nearest vertical couplings (k to k+-2)
+    dropped: the tridiagonal part of H_z, whose diagonal still holds their
+    contribution. For the 7-point operator that is H_z itself.
     ``sub[k]`` couples k to k-1 (zero at k = 0), ``sup[k]`` couples k to k+1.
     """
     nz, ncol = delta.shape
@@ -94,7 +113,18 @@ def column_tridiagonal(level, kh, kv, delta):
         diag[1:] += kv
         sup[:-1] = -kv
         sub[1:] = -kv
+    if kv2 is not None and nz > 2:
+        diag[:-2] += kv2
+        diag[2:] += kv2
     return sub, diag, sup
+
+
+def coarsen_kv2(kv2, childs):
+    """Next-to-nearest vertical couplings scale like K_v (Eq. DH_ratios: the
+    vertical part scales with dx^2): the coarse one is the sum over the four
+    children."""
+    c00, c10, c01, c11 = childs
+    return ((kv2[:, c00] + kv2[:, c10]) + kv2[:, c01]) + kv2[:, c11]
 
 
 def coarsen(kh, kv, delta, childs):
@@ -115,29 +145,36 @@ def coarsen(kh, kv, delta, childs):
 class Hierarchy:
     """All multigrid levels of one operator: tables and coefficients per level."""
 
-    def __init__(self, levels, parents, childs, kh, kv, delta, dtype=np.float64):
+    def __init__(self, levels, parents, childs, kh, kv, delta, dtype=np.float64, kv2=None):
         self.levels, self.parents, self.childs = levels, parents, childs
         self.coeffs = [(kh, kv, delta)]
+        self.kv2s = [kv2]
         for l in range(len(levels) - 1):
             self.coeffs.append(coarsen(*self.coeffs[-1], childs[l]))
+            self.kv2s.append(None if kv2 is None else coarsen_kv2(self.kv2s[-1], childs[l]))
         self.dtype = np.dtype(dtype)
         if self.dtype != np.float64:
             # coarse coefficients are made in float64 and rounded once
             self.coeffs = [tuple(a.astype(dtype) for a in c) for c in self.coeffs]
+            self.kv2s = [None if a is None else a.astype(dtype) for a in self.kv2s]
 
     @property
     def nlevels(self):
         return len(self.levels)
 
     def apply(self, l, x):
-        return apply(self.levels[l], *self.coeffs[l], x)
+        return apply(self.levels[l], *self.coeffs[l], x, kv2=self.kv2s[l])
 
     def column_tridiagonal(self, l):
-        return column_tridiagonal(self.levels[l], *self.coeffs[l])
+        return column_tridiagonal(self.levels[l], *self.coeffs[l], kv2=self.kv2s[l])
+
+    def assemble(self, l):
+        return assemble(self.levels[l], *self.coeffs[l], kv2=self.kv2s[l])
 
     def astype(self, dtype):
         h = Hierarchy.__new__(Hierarchy)
         h.levels, h.parents, h.childs = self.levels, self.parents, self.childs
         h.dtype = np.dtype(dtype)
         h.coeffs = [tuple(a.astype(dtype) for a in c) for c in self.coeffs]
+        h.kv2s = [None if a is None else a.astype(dtype) for a in self.kv2s]
         return h

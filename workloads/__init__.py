@@ -17,7 +17,11 @@ H of Section 3.4:
 * one vertical coupling per interior vertical face, ``kv[nz-1][ncol]`` (face
   between levels k and k+1), ``w_v * g(k) * (1 + 0.1 u)`` with ``g = 1`` or
   the height grading ``g(k) = exp(-k / 20)``;
-* a zero-order term ``delta[nz][ncol] ~ U[0.5, 1.5]``.
+* a zero-order term ``delta[nz][ncol] ~ U[0.5, 1.5]``;
+* for the 9-cell stencil of Section 3.5 (each cell also coupled to the cells
+  two levels above and below), a next-to-nearest vertical coupling
+  ``kv2[nz-2][ncol]`` (levels k and k+2), ``w_v2 * g(k) * (1 + 0.1 u)``,
+  drawn from its own seed so the other draws do not change.
 
 Vectors are ``[batch][nz][ncol]`` with the column index fastest.
 """
@@ -31,6 +35,7 @@ SEED_OP = 0
 SEED_B = 1
 SEED_G = 2
 SEED_FD = 3
+SEED_K2 = 4
 
 
 @dataclasses.dataclass(frozen=True)
@@ -45,6 +50,7 @@ class Workload:
     graded: bool
     nlevels: int
     batch: int = 1
+    w_v2: float = 0.0   # > 0: 9-cell stencil with next-to-nearest vertical couplings
 
     @property
     def ncol(self) -> int:
@@ -63,8 +69,13 @@ C96x30 = Workload("C96x30", 96, 30, 1.0, 1000.0, False, 5)
 C192x70 = Workload("C192x70", 192, 70, 1.0, 1000.0, True, 6)
 C384x70 = Workload("C384x70", 384, 70, 1.0, 1000.0, True, 7, batch=4)
 C6x8 = Workload("C6x8", 6, 8, 1.0, 1000.0, False, 2)
+# 9-cell stencil versions: next-to-nearest vertical couplings 1 % of the
+# nearest ones (the paper's scalings put the term they come from, D_1^z, at
+# N^2 dz / g ~ 2e-3 of D_2^z on its grid; 1e-2 exercises them a little harder)
+C12x10_9 = Workload("C12x10_9", 12, 10, 1.0, 100.0, False, 3, w_v2=1.0)
+C192x70_9 = Workload("C192x70_9", 192, 70, 1.0, 1000.0, True, 6, w_v2=10.0)
 
-ALL = {w.name: w for w in (C12x10, C96x30, C192x70, C384x70, C6x8)}
+ALL = {w.name: w for w in (C12x10, C96x30, C192x70, C384x70, C6x8, C12x10_9, C192x70_9)}
 
 
 def coefficients(N: int, nz: int, w_h: float = 1.0, w_v: float = 100.0,
@@ -88,6 +99,23 @@ def coefficients(N: int, nz: int, w_h: float = 1.0, w_v: float = 100.0,
 
 def workload_coefficients(w: Workload, seed: int = SEED_OP):
     return coefficients(w.N, w.nz, w.w_h, w.w_v, w.graded, seed)
+
+
+def next_nearest(N: int, nz: int, w_v2: float, graded: bool = False, seed: int = SEED_K2):
+    """``kv2[nz-2][ncol]``: coupling between levels k and k+2 (9-cell stencil)."""
+    ncol = 6 * N * N
+    m = max(nz - 2, 0)
+    rng = np.random.default_rng(seed)
+    u = rng.random((m, ncol))
+    grade = np.ones(m)
+    if graded:
+        grade = np.exp(-np.arange(m, dtype=np.float64) / 20.0)
+    return w_v2 * grade[:, None] * (1.0 + 0.1 * u)
+
+
+def workload_kv2(w: Workload):
+    """The workload's next-to-nearest couplings, or None for the 7-point stencil."""
+    return next_nearest(w.N, w.nz, w.w_v2, w.graded) if w.w_v2 > 0 else None
 
 
 def rhs(N: int, nz: int, batch: int = 1, seed: int = SEED_B) -> np.ndarray:
