@@ -88,6 +88,8 @@ typedef struct {
     int32_t mg_precision; /* HELMHOLTZ_FP64 or HELMHOLTZ_FP32 (V-cycle arithmetic)           */
     int32_t cg_variant;   /* HELMHOLTZ_CG_STANDARD, _CG_FLEXIBLE or HELMHOLTZ_BICGSTAB       */
     int32_t max_batch;    /* largest batch any call will pass, >= 1                          */
+    int32_t stencil;      /* 7 (or 0): nearest vertical couplings only; 9: also couplings two
+                             levels apart (Section 3.5), created with helmholtz_create9     */
 } helmholtz_config;
 
 /* Bytes of device workspace that helmholtz_create needs for cfg; 0 if cfg is
@@ -108,6 +110,21 @@ size_t helmholtz_workspace_bytes(const helmholtz_config* cfg);
 int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double* kv,
                      const double* delta, void* workspace, size_t workspace_bytes,
                      helmholtz_stream_t stream, helmholtz_t* out);
+
+/* The 9-cell stencil of Section 3.5: H also couples each cell to the cells two
+ * levels above and below,
+ *   (H x)[k,c] += kv2[k,c] (x[k,c] - x[k+2,c])   (k < nz-2)
+ *              + kv2[k-2,c] (x[k,c] - x[k-2,c])  (k > 1),
+ * and the smoother's column matrix drops those couplings but keeps their
+ * contribution to the diagonal (Section 3.6: the block-tridiagonal Hz of the
+ * block-Jacobi step), so a sweep no longer solves a column exactly. Coarse
+ * levels sum kv2 over the four children, like kv.
+ *   kv2   [nz-2][ncol]  >= 0 (may be NULL if nz <= 2)
+ * cfg->stencil must be 9; the other arguments are those of helmholtz_create,
+ * which rejects stencil 9. */
+int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const double* kv,
+                      const double* kv2, const double* delta, void* workspace,
+                      size_t workspace_bytes, helmholtz_stream_t stream, helmholtz_t* out);
 
 /* Release host state (handle, pinned scalars). Never touches the workspace. */
 int helmholtz_destroy(helmholtz_t h);
@@ -160,6 +177,13 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
  * Asynchronous. */
 int helmholtz_face_grad(helmholtz_t h, const double* lam, const double* x, int32_t batch,
                         double* g_kh, double* g_kv, double* g_delta, helmholtz_stream_t stream);
+
+/* helmholtz_face_grad for a 9-cell handle, adding g_kv2 [nz-2][ncol] (the
+ * same flux-form rule on the faces k | k+2, summed over the batch; may be NULL
+ * to skip it, must be NULL for a 7-point handle). */
+int helmholtz_face_grad9(helmholtz_t h, const double* lam, const double* x, int32_t batch,
+                         double* g_kh, double* g_kv, double* g_kv2, double* g_delta,
+                         helmholtz_stream_t stream);
 
 /* Mesh tables of C<N> as built by the library (host arrays, int32):
  *   nbr    [4][6N^2]  neighbour column in directions E, W, N, S

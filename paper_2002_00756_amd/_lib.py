@@ -30,13 +30,15 @@ class Config(ctypes.Structure):
                 ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
                 ("n_coarse", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("mg_precision", ctypes.c_int32), ("cg_variant", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("stencil", ctypes.c_int32)]
 
 
 SIGNATURES = {
     "helmholtz_workspace_bytes": (_c_size, [ctypes.POINTER(Config)]),
     "helmholtz_create": (_c_int, [ctypes.POINTER(Config), _dp, _dp, _dp, _vp, _c_size, _vp,
                                   ctypes.POINTER(_vp)]),
+    "helmholtz_create9": (_c_int, [ctypes.POINTER(Config), _dp, _dp, _dp, _dp, _vp, _c_size,
+                                   _vp, ctypes.POINTER(_vp)]),
     "helmholtz_destroy": (_c_int, [_vp]),
     "helmholtz_apply": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_vcycle": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
@@ -44,6 +46,7 @@ SIGNATURES = {
     "helmholtz_solve": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                  _i32p, _f64p, _vp]),
     "helmholtz_face_grad": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _dp, _dp, _dp, _vp]),
+    "helmholtz_face_grad9": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _dp, _dp, _dp, _dp, _vp]),
     "helmholtz_mesh_tables": (_c_int, [ctypes.c_int32, _i32p, _i32p, _i32p]),
     "helmholtz_strerror": (ctypes.c_char_p, [_c_int]),
     "helmholtz_profile_enable": (_c_int, [_vp, _c_int]),

@@ -33,6 +33,7 @@ struct LevelData {
     T* dl = nullptr;  // [nvp]
     T* cc = nullptr;  // [nvp]
     T* mm = nullptr;  // [nvp]
+    T* kv2 = nullptr; // [nvp]     9-cell stencil only
     T* b = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
     T* x = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
     T* t = nullptr;   // [B][nvp]   ping-pong partner of x
@@ -76,6 +77,7 @@ bool config_ok(const helmholtz_config* c) {
         c->cg_variant != HELMHOLTZ_BICGSTAB)
         return false;
     if (c->max_batch < 1) return false;
+    if (c->stencil != 0 && c->stencil != 7 && c->stencil != 9) return false;
     return true;
 }
 
@@ -95,6 +97,7 @@ int shape_error(const helmholtz_config* c) {
 struct helmholtz_s {
     helmholtz_config cfg{};
     int L = 0, nz = 0, B = 0;
+    bool nine = false;  // 9-cell stencil (next-to-nearest vertical couplings)
     int64_t n = 0;    // unknowns per right-hand side on the finest level
     int64_t nvp = 0;  // tiled length of a finest-level vector (n plus padding)
     std::vector<Level> lev;
@@ -156,6 +159,10 @@ void layout(helmholtz_s* h, Carver& cv) {
         v.f.dl = v.f.kh + 3 * nv;
         v.f.cc = v.f.kh + 4 * nv;
         v.f.mm = v.f.kh + 5 * nv;
+        if (h->nine) {
+            v.d.kv2 = cv.take<double>(nv);
+            v.f.kv2 = cv.take<float>(nv);
+        }
         if (l > 0) {
             v.d.b = cv.take<double>(size_t(B) * nv);
             v.d.x = cv.take<double>(size_t(B) * nv);
@@ -192,6 +199,7 @@ void init_shape(helmholtz_s* h, const helmholtz_config* cfg) {
     h->L = cfg->nlevels;
     h->nz = cfg->nz;
     h->B = cfg->max_batch;
+    h->nine = cfg->stencil == 9;
     h->lev.assign(h->L, Level{});
     for (int l = 0; l < h->L; ++l) {
         Level& v = h->lev[l];
@@ -270,7 +278,8 @@ LevelView<T> view(const helmholtz_s* h, int l) {
         if constexpr (std::is_same<T, double>::value) return v.d;
         else return v.f;
     }();
-    return LevelView<T>{v.ncol, h->nz, v.nvp, v.nbr, v.fface, d.kh, d.kv, d.dl, d.cc, d.mm};
+    return LevelView<T>{v.ncol, h->nz, v.nvp, v.nbr, v.fface, d.kh, d.kv, d.dl, d.cc, d.mm,
+                        d.kv2};
 }
 
 template <typename T>
@@ -291,11 +300,18 @@ void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T
     const int32_t* par = (l + 1 < h->L) ? v.parent : nullptr;
     const int nvp_c = (l + 1 < h->L) ? h->lev[l + 1].nvp : 0;
     const bool prof = (l == 0 && MODE == kPlain) && prof_begin(h, HELMHOLTZ_PROF_SWEEP_FINE, s);
-    hipLaunchKernelGGL((k_sweep<T, JMAX, MODE, TC, kBlock>), dim3(ntile * batch), dim3(kBlock),
-                       Tile::lds_bytes(h->nz), s, view<T>(h, l), b, x, xc, par, nvp_c,
-                       y, T(h->cfg.omega), batch, active, sweep_mid(h->nz));
-    if (prof)  // b, x, kh[2], cc, mm read; x_new written
-        prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE, 7.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(ntile * batch), dim3(kBlock), Tile::lds_bytes(h->nz), s,
+                           view<T>(h, l), b, x, xc, par, nvp_c, y, T(h->cfg.omega), batch, active,
+                           sweep_mid(h->nz));
+    };
+    if (h->nine)
+        go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, true>);
+    else
+        go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false>);
+    if (prof)  // b, x, kh[2], cc, mm (, kv2) read; x_new written
+        prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE,
+                 (h->nine ? 8.0 : 7.0) * sizeof(T) * double(batch) * h->nz * v.ncol, s);
 }
 
 // Large levels: 32-column tiles (8 level groups, several workgroups per CU).
@@ -360,18 +376,20 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
     const uintptr_t al = 2 * sizeof(T);
     const bool pair = reinterpret_cast<uintptr_t>(b) % al == 0 &&
                       reinterpret_cast<uintptr_t>(x) % al == 0;
-    if (x && pair)
-        hipLaunchKernelGGL((k_resid_restrict<T, false, true>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
-    else if (x)
-        hipLaunchKernelGGL((k_resid_restrict<T, false, false>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
-    else if (pair)
-        hipLaunchKernelGGL((k_resid_restrict<T, true, true>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
-    else
-        hipLaunchKernelGGL((k_resid_restrict<T, true, false>), grid, dim3(kBlock), 0, s,
-                           view<T>(h, l), c.child, c.ncol, c.nvp, b, x, bc, batch, kchunk, nkc, active);
+    auto go = [&](auto kern) {
+        hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), c.child, c.ncol, c.nvp,
+                           b, x, bc, batch, kchunk, nkc, active);
+    };
+    if (!x) {
+        if (pair) go(k_resid_restrict<T, true, true>);
+        else go(k_resid_restrict<T, true, false>);
+    } else if (h->nine) {
+        if (pair) go(k_resid_restrict<T, false, true, true>);
+        else go(k_resid_restrict<T, false, false, true>);
+    } else {
+        if (pair) go(k_resid_restrict<T, false, true>);
+        else go(k_resid_restrict<T, false, false>);
+    }
 }
 
 template <typename T>
@@ -386,14 +404,24 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
         hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), x, y, w, batch, nkc,
                            cg_state(h), active);
     };
-    switch (dot) {
-        case kDotXY: go(k_apply<T, kDotXY, kApplyChunk>); break;
-        case kDotWY: go(k_apply<T, kDotWY, kApplyChunk>); break;
-        case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk>); break;
-        default: go(k_apply<T, kDotNone, kApplyChunk>); break;
+    if (h->nine) {
+        switch (dot) {
+            case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, true>); break;
+            case kDotWY: go(k_apply<T, kDotWY, kApplyChunk, true>); break;
+            case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk, true>); break;
+            default: go(k_apply<T, kDotNone, kApplyChunk, true>); break;
+        }
+    } else {
+        switch (dot) {
+            case kDotXY: go(k_apply<T, kDotXY, kApplyChunk>); break;
+            case kDotWY: go(k_apply<T, kDotWY, kApplyChunk>); break;
+            case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk>); break;
+            default: go(k_apply<T, kDotNone, kApplyChunk>); break;
+        }
     }
-    if (prof)  // x, kh[2], kv, delta read; y written
-        prof_end(h, HELMHOLTZ_PROF_APPLY_FINE, 6.0 * sizeof(T) * double(batch) * h->nz * v.ncol, s);
+    if (prof)  // x, kh[2], kv, delta (, kv2) read; y written
+        prof_end(h, HELMHOLTZ_PROF_APPLY_FINE,
+                 (h->nine ? 7.0 : 6.0) * sizeof(T) * double(batch) * h->nz * v.ncol, s);
 }
 
 // ---- V-cycle (Algorithm 1) ------------------------------------------------
@@ -638,9 +666,21 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
                      helmholtz_stream_t stream_, helmholtz_t* out) {
     if (!out) return HELMHOLTZ_EINVAL;
     *out = nullptr;
+    if (config_ok(cfg) && cfg->stencil == 9) return HELMHOLTZ_EINVAL;  // needs kv2
+    return helmholtz_create9(cfg, kh, kv, nullptr, delta, workspace, workspace_bytes, stream_,
+                             out);
+}
+
+int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const double* kv,
+                      const double* kv2, const double* delta, void* workspace,
+                      size_t workspace_bytes, helmholtz_stream_t stream_, helmholtz_t* out) {
+    if (!out) return HELMHOLTZ_EINVAL;
+    *out = nullptr;
     if (!config_ok(cfg)) return HELMHOLTZ_EINVAL;
     if (int e = shape_error(cfg)) return e;
     if (!kh || !delta || (cfg->nz > 1 && !kv)) return HELMHOLTZ_EINVAL;
+    const bool nine = cfg->stencil == 9;
+    if (nine != (kv2 != nullptr) && !(nine && cfg->nz <= 2)) return HELMHOLTZ_EINVAL;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % HELMHOLTZ_WORKSPACE_ALIGN))
         return HELMHOLTZ_EWORKSPACE;
     const size_t need = helmholtz_workspace_bytes(cfg);
@@ -721,14 +761,16 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
         Level& v = h->lev[0];
         const int64_t nv = int64_t(nz) * v.ncol;
         hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(nv)), dim3(kBlock), 0, s, v.ncol, nz,
-                           v.nvp, kh, kv, delta, v.d.kh, v.d.kv, v.d.dl, h->flags);
+                           v.nvp, kh, kv, delta, kv2, v.d.kh, v.d.kv, v.d.dl,
+                           kv2 ? v.d.kv2 : nullptr, h->flags);
     }
     for (int l = 1; l < h->L; ++l) {
         Level& f = h->lev[l - 1];
         Level& c = h->lev[l];
         const int64_t nv = int64_t(nz) * c.ncol;
         hipLaunchKernelGGL(k_coarsen, dim3(grid_for(nv)), dim3(kBlock), 0, s, c.ncol, nz, f.nvp,
-                           c.nvp, c.child, f.d.kh, f.d.kv, f.d.dl, c.d.kh, c.d.kv, c.d.dl);
+                           c.nvp, c.child, f.d.kh, f.d.kv, f.d.dl, f.d.kv2, c.d.kh, c.d.kv,
+                           c.d.dl, c.d.kv2);
     }
     for (int l = 0; l < h->L; ++l) {
         Level& v = h->lev[l];
@@ -741,6 +783,7 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
         convert<double, float>(v.d.dl, v.f.dl, nv, s);
         convert<double, float>(v.d.cc, v.f.cc, nv, s);
         convert<double, float>(v.d.mm, v.f.mm, nv, s);
+        if (h->nine) convert<double, float>(v.d.kv2, v.f.kv2, nv, s);
     }
     if (last_error() != HELMHOLTZ_OK) return fail(HELMHOLTZ_EHIP);
     if (hipMemcpyAsync(h->hflags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -945,14 +988,21 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
 
 int helmholtz_face_grad(helmholtz_t h, const double* lam, const double* x, int32_t batch,
                         double* g_kh, double* g_kv, double* g_delta, helmholtz_stream_t stream) {
+    return helmholtz_face_grad9(h, lam, x, batch, g_kh, g_kv, nullptr, g_delta, stream);
+}
+
+int helmholtz_face_grad9(helmholtz_t h, const double* lam, const double* x, int32_t batch,
+                         double* g_kh, double* g_kv, double* g_kv2, double* g_delta,
+                         helmholtz_stream_t stream) {
     if (int e = check_batch(h, batch)) return e;
     if (!lam || !x || !g_kh || !g_delta || (h->nz > 1 && !g_kv)) return HELMHOLTZ_EINVAL;
+    if (g_kv2 && !h->nine) return HELMHOLTZ_EINVAL;
     const Level& v = h->lev[0];
     const int64_t total = int64_t(h->nz) * v.ncol;
     const int grid = int((total + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_face_grad, dim3(grid), dim3(kBlock), 0,
                        reinterpret_cast<hipStream_t>(stream), v.ncol, h->nz, v.nbr, lam, x, batch,
-                       g_kh, g_kv, g_delta);
+                       g_kh, g_kv, g_delta, h->nz > 2 ? g_kv2 : nullptr);
     return last_error();
 }
 

@@ -14,6 +14,8 @@
 //   kv             [nvp]               face k|k+1; row nz-1 is zero (no flux
 //                                      through the top), so loads need no guard
 //   dl (delta)     [nvp]
+//   kv2            [nvp]               9-cell stencil only: coupling of levels
+//                                      k and k+2; rows nz-2, nz-1 are zero
 //   cc, mm         [nvp]               factors of the column operator (below)
 //   nbr            [4][ncol]           E, W, N, S neighbour column
 //   fface          [2][ncol]           offset in kh of the W and S face at
@@ -25,11 +27,13 @@
 // keep the natural [batch][nz][ncol] layout; the kernels that take them in or
 // hand them out convert on the fly.
 //
-// Column factorisation. The smoother solves with the column operator Hz (all
-// couplings inside a column plus the full diagonal of H; Section 3.5, Eq.
-// jacobi) by an LU factorisation computed once per operator (the paper
-// stores the same factors; Section 3.8). Pivots are computed in a form free
-// of cancellation: with s_k = delta_k + sum of the 4 horizontal couplings,
+// Column factorisation. The smoother solves with the column operator Hz (the
+// couplings between neighbouring levels of a column plus the full diagonal of
+// H; Section 3.5, Eq. jacobi; with the 9-cell stencil the couplings two
+// levels apart are dropped from it but stay in its diagonal, Section 3.6) by
+// an LU factorisation computed once per operator (the paper stores the same
+// factors; Section 3.8). Pivots are computed in a form free of cancellation:
+// with s_k = delta_k + sum of the 4 horizontal couplings (+ kv2_k + kv2_{k-2}),
 // the top-down pivot excess is e_0 = s_0, e_k = s_k + kv_{k-1} e_{k-1} /
 // (e_{k-1} + kv_{k-1}), pivot p_k = e_k + kv_k. Stored: mm_k = 1/p_k and
 // cc_k = kv_k / p_k, so that forward elimination is t_k = r_k + cc_{k-1} t_{k-1}
@@ -75,6 +79,7 @@ struct LevelView {
     const T* __restrict__ dl;
     const T* __restrict__ cc;
     const T* __restrict__ mm;
+    const T* __restrict__ kv2;  // null for the 7-point stencil
 };
 
 // ---------------------------------------------------------------------------
@@ -224,7 +229,7 @@ struct SweepTile {
 };
 
 template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = kBlock,
-          int CH_ = 0>
+          int CH_ = 0, bool K2 = false>
 __global__ void __launch_bounds__(NT)
 k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         const T* __restrict__ xc, const int32_t* __restrict__ parent, int nvp_c,
@@ -286,6 +291,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
 #pragma unroll
     for (int j0 = 0; j0 < JMAX; j0 += CH) {
         T vb[CH], vc[CH], vm[CH], vx[CH][5], vk[CH][4];
+        T v2[CH];  // 9-cell: kv2_k x_{k+2} + kv2_{k-2} x_{k-2}
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
             const int j = j0 + jj;
@@ -295,6 +301,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
             for (int d = 0; d < 5; ++d) vx[jj][d] = T(0);
 #pragma unroll
             for (int d = 0; d < 4; ++d) vk[jj][d] = T(0);
+            v2[jj] = T(0);
             if (j < JMAX && k < nz && valid) {
                 const int o = ob + kTile * k;
                 vb[jj] = b[o];
@@ -308,6 +315,10 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
 #pragma unroll
                     for (int d = 0; d < 4; ++d) vx[jj][d] = xv(k, nb[d], pn[d]);
                     vx[jj][4] = xv(k, ob, pn[4]);
+                    if constexpr (K2) {
+                        if (k + 2 < nz) v2[jj] = L.kv2[o] * xv(k + 2, ob, pn[4]);
+                        if (k >= 2) v2[jj] += L.kv2[o - 2 * kTile] * xv(k - 2, ob, pn[4]);
+                    }
                 }
             }
         }
@@ -320,6 +331,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
                 if (MODE != kZero)
                     r += vk[jj][0] * vx[jj][0] + vk[jj][1] * vx[jj][1] + vk[jj][2] * vx[jj][2] +
                          vk[jj][3] * vx[jj][3];
+                if (K2 && MODE != kZero) r += v2[jj];
                 xo[j] = vx[jj][4];
                 mo[j] = vm[jj];
                 R[k * TC + lc] = r;
@@ -513,7 +525,7 @@ k_finalize(CgState st, int mode, int cnt, int seq) {
 // kDotWYYY w . y and y . y (BiCGStab: (t, s), (t, t)). Partial sums per block.
 enum { kDotNone = 0, kDotXY = 1, kDotWY = 2, kDotWYYY = 3 };
 
-template <typename T, int DOT, int KC>
+template <typename T, int DOT, int KC, bool K2 = false>
 __global__ void __launch_bounds__(kBlock)
 k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
         int batch, int nkc, CgState st, const int* __restrict__ active) {
@@ -550,6 +562,18 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
             const int k = k0 - 1 + j;
             kvv[j] = (k >= 0 && k < nz) ? L.kv[ob + kTile * k] : T(0);
         }
+        // 9-cell: x at k0-2 and k0+KC+1 (xc holds k0-1 .. k0+KC), kv2 at
+        // k0-2 .. k0+KC-1
+        T xlo = T(0), xhi = T(0), k2v[KC + 2];
+        if constexpr (K2) {
+            if (k0 >= 2) xlo = x[ob + kTile * (k0 - 2)];
+            if (k0 + KC + 1 < nz) xhi = x[ob + kTile * (k0 + KC + 1)];
+#pragma unroll
+            for (int j = 0; j < KC + 2; ++j) {
+                const int k = k0 - 2 + j;
+                k2v[j] = (k >= 0 && k < nz) ? L.kv2[ob + kTile * k] : T(0);
+            }
+        }
 #pragma unroll
         for (int j = 0; j < KC; ++j) {
             const int k = k0 + j;
@@ -577,6 +601,13 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
                 for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
                 v += kvv[j + 1] * (xo - xc[j + 2]);
                 v += kvv[j] * (xo - xc[j]);
+                if constexpr (K2) {
+                    // x[k-2] and x[k+2] (xc[i] holds x[k0-1+i])
+                    const T xm2 = j >= 1 ? xc[j - 1] : xlo;
+                    const T xp2 = j + 3 <= KC + 1 ? xc[j + 3] : xhi;
+                    v += k2v[j + 2] * (xo - xp2);
+                    v += k2v[j] * (xo - xm2);
+                }
                 y[ob + kTile * k] = v;
                 if (DOT == kDotXY) acc += double(xo) * double(v);
                 if (DOT >= kDotWY) acc += double(w[ob + kTile * k]) * double(v);
@@ -631,7 +662,7 @@ __device__ __forceinline__ void load_pair(const T* __restrict__ p, int64_t i, T&
     }
 }
 
-template <typename T, bool ZEROX, bool PAIR>
+template <typename T, bool ZEROX, bool PAIR, bool K2 = false>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
                  const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
@@ -694,6 +725,23 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
     }
     load_pair<T, PAIR>(x, kTile * k0 + cb[0], xo[0], xo[1]);
     load_pair<T, PAIR>(x, kTile * k0 + cb[2], xo[2], xo[3]);
+    // 9-cell: window x[k-2], kv2[k-2], kv2[k-1] of the four children
+    T xm2[4] = {T(0), T(0), T(0), T(0)}, k2m2[4] = {T(0), T(0), T(0), T(0)};
+    T k2m1[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (K2) {
+        if (k0 >= 2) {
+            const int r2 = kTile * (k0 - 2);
+            load_pair<T, PAIR>(x, r2 + cb[0], xm2[0], xm2[1]);
+            load_pair<T, PAIR>(x, r2 + cb[2], xm2[2], xm2[3]);
+            load_pair<T, PAIR>(F.kv2, r2 + cb[0], k2m2[0], k2m2[1]);
+            load_pair<T, PAIR>(F.kv2, r2 + cb[2], k2m2[2], k2m2[3]);
+        }
+        if (k0 >= 1) {
+            const int r1 = kTile * (k0 - 1);
+            load_pair<T, PAIR>(F.kv2, r1 + cb[0], k2m1[0], k2m1[1]);
+            load_pair<T, PAIR>(F.kv2, r1 + cb[2], k2m1[2], k2m1[3]);
+        }
+    }
     for (int k = k0; k < k1; ++k) {
         const int r = kTile * k;
         T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8];
@@ -720,9 +768,27 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
         }
 #pragma unroll
         for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
+        T k2[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (K2) {
+            T xp2[4] = {T(0), T(0), T(0), T(0)};
+            if (k + 2 < nz) {
+                load_pair<T, PAIR>(x, r + 2 * kTile + cb[0], xp2[0], xp2[1]);
+                load_pair<T, PAIR>(x, r + 2 * kTile + cb[2], xp2[2], xp2[3]);
+            }
+            load_pair<T, PAIR>(F.kv2, r + cb[0], k2[0], k2[1]);
+            load_pair<T, PAIR>(F.kv2, r + cb[2], k2[2], k2[3]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc -= k2[s] * (xo[s] - xp2[s]) + k2m2[s] * (xo[s] - xm2[s]);
+        }
         bc[r] = acc;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
+            if constexpr (K2) {
+                xm2[s] = xdn[s];
+                k2m2[s] = k2m1[s];
+                k2m1[s] = k2[s];
+            }
             xdn[s] = xo[s];
             xo[s] = xup[s];
             kvdn[s] = vkv[s];
@@ -755,8 +821,8 @@ k_prolong(int ncol, int nz, int nvp, int nvp_c, const int32_t* __restrict__ pare
 __global__ void __launch_bounds__(kBlock)
 k_setup_fine(int ncol, int nz, int nvp, const double* __restrict__ kh_in,
              const double* __restrict__ kv_in, const double* __restrict__ dl_in,
-             double* __restrict__ kh, double* __restrict__ kv, double* __restrict__ dl,
-             int* __restrict__ flags) {
+             const double* __restrict__ kv2_in, double* __restrict__ kh, double* __restrict__ kv,
+             double* __restrict__ dl, double* __restrict__ kv2, int* __restrict__ flags) {
     const int64_t total = int64_t(nz) * ncol;
     int bad = 0;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
@@ -772,6 +838,12 @@ k_setup_fine(int ncol, int nz, int nvp, const double* __restrict__ kh_in,
         dl[o] = d;
         if (!isfinite(e) || !isfinite(n) || !isfinite(v) || !isfinite(d)) bad |= 1;
         if (!(e >= 0.0) || !(n >= 0.0) || !(v >= 0.0) || !(d > 0.0)) bad |= 2;
+        if (kv2) {
+            const double v2 = (k + 2 < nz) ? kv2_in[i] : 0.0;
+            kv2[o] = v2;
+            if (!isfinite(v2)) bad |= 1;
+            if (!(v2 >= 0.0)) bad |= 2;
+        }
     }
     if (bad) atomicOr(flags, bad);
 }
@@ -782,8 +854,9 @@ k_setup_fine(int ncol, int nz, int nvp, const double* __restrict__ kh_in,
 __global__ void __launch_bounds__(kBlock)
 k_coarsen(int ncol_c, int nz, int nvp_f, int nvp_c, const int32_t* __restrict__ child,
           const double* __restrict__ khf, const double* __restrict__ kvf,
-          const double* __restrict__ dlf, double* __restrict__ khc, double* __restrict__ kvc,
-          double* __restrict__ dlc) {
+          const double* __restrict__ dlf, const double* __restrict__ kv2f,
+          double* __restrict__ khc, double* __restrict__ kvc, double* __restrict__ dlc,
+          double* __restrict__ kv2c) {
     const int64_t total = int64_t(nz) * ncol_c;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * kBlock) {
@@ -799,6 +872,7 @@ k_coarsen(int ncol_c, int nz, int nvp_f, int nvp_c, const int32_t* __restrict__ 
         khc[int64_t(nvp_c) + o] = 0.5 * (khfN[c01] + khfN[c11]);
         kvc[o] = ((kvf[c00] + kvf[c10]) + kvf[c01]) + kvf[c11];
         dlc[o] = ((dlf[c00] + dlf[c10]) + dlf[c01]) + dlf[c11];
+        if (kv2c) kv2c[o] = ((kv2f[c00] + kv2f[c10]) + kv2f[c01]) + kv2f[c11];
     }
 }
 
@@ -813,8 +887,11 @@ k_factor(LevelView<double> L, int mid, double* __restrict__ cc, double* __restri
     const double* khN = L.kh + L.nvp;
     auto s_of = [&](int k) {
         const int o = ob + kTile * k;
-        return L.dl[o] + L.kh[o] + L.kh[fW + uint32_t(kTile * k)] + khN[o] +
-               L.kh[fS + uint32_t(kTile * k)];
+        double v = L.dl[o] + L.kh[o] + L.kh[fW + uint32_t(kTile * k)] + khN[o] +
+                   L.kh[fS + uint32_t(kTile * k)];
+        // 9-cell: the dropped couplings two levels apart stay in the diagonal
+        if (L.kv2) v += L.kv2[o] + (k >= 2 ? L.kv2[o - 2 * kTile] : 0.0);
+        return v;
     };
     auto kv_of = [&](int k) { return L.kv[ob + kTile * k]; };
     auto put = [&](int k, double m, double cv) {
@@ -1076,11 +1153,12 @@ k_bicg_xr(double* __restrict__ x, double* __restrict__ r, const double* __restri
 
 // ---------------------------------------------------------------------------
 // Face-coefficient gradients of L = g . x (summed over the batch), written in
-// the ABI layout: g_kh[2][nz][ncol], g_kv[nz-1][ncol], g_delta[nz][ncol].
+// the ABI layout: g_kh[2][nz][ncol], g_kv[nz-1][ncol], g_delta[nz][ncol] and,
+// for the 9-cell stencil, g_kv2[nz-2][ncol] (gkv2 non-null).
 __global__ void __launch_bounds__(kBlock)
 k_face_grad(int ncol, int nz, const int32_t* __restrict__ nbr, const double* __restrict__ lam,
             const double* __restrict__ x, int batch, double* __restrict__ gkh,
-            double* __restrict__ gkv, double* __restrict__ gdl) {
+            double* __restrict__ gkv, double* __restrict__ gdl, double* __restrict__ gkv2) {
     const int64_t total = int64_t(nz) * ncol;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t i = int64_t(lb) * kBlock + threadIdx.x;
@@ -1089,7 +1167,7 @@ k_face_grad(int ncol, int nz, const int32_t* __restrict__ nbr, const double* __r
     const int c = int(i % ncol);
     const int e = nbr[c], nn = nbr[2 * ncol + c];
     const int64_t row = k * ncol;
-    double ge = 0.0, gn = 0.0, gv = 0.0, gd = 0.0;
+    double ge = 0.0, gn = 0.0, gv = 0.0, gd = 0.0, gv2 = 0.0;
     for (int bi = 0; bi < batch; ++bi) {
         const double* l = lam + int64_t(bi) * total;
         const double* xx = x + int64_t(bi) * total;
@@ -1097,11 +1175,14 @@ k_face_grad(int ncol, int nz, const int32_t* __restrict__ nbr, const double* __r
         ge -= (lc - l[row + e]) * (xc - xx[row + e]);
         gn -= (lc - l[row + nn]) * (xc - xx[row + nn]);
         if (k + 1 < nz) gv -= (lc - l[row + ncol + c]) * (xc - xx[row + ncol + c]);
+        if (gkv2 && k + 2 < nz)
+            gv2 -= (lc - l[row + 2 * ncol + c]) * (xc - xx[row + 2 * ncol + c]);
         gd -= lc * xc;
     }
     gkh[i] = ge;
     gkh[total + i] = gn;
     if (k + 1 < nz) gkv[i] = gv;
+    if (gkv2 && k + 2 < nz) gkv2[i] = gv2;
     gdl[i] = gd;
 }
 

@@ -58,7 +58,9 @@ class Operator:
     ("standard", "flexible"), or right-preconditioned BiCGStab ("bicgstab",
     where ``iters`` counts iterations of two products with H each). With
     ``nlevels=1`` the preconditioner is P_H^(Jac)(omega, n_coarse), and
-    ``vcycle`` alone is the preconditioner-only solver PreOnly.
+    ``vcycle`` alone is the preconditioner-only solver PreOnly. ``kv2``
+    (``[nz-2][ncol]``) selects the 9-cell stencil with couplings two levels
+    apart; ``face_grad`` then also returns their gradient.
     """
 
     _KRYLOV = {"standard": _lib.CG_STANDARD, "flexible": _lib.CG_FLEXIBLE,
@@ -71,7 +73,8 @@ class Operator:
         return cls._KRYLOV[cg]
 
     def __init__(self, N, nz, kh, kv, delta, nlevels, n_pre=2, n_post=2, n_coarse=4,
-                 omega=0.8, precision="fp64", cg="standard", max_batch=1, device="cuda"):
+                 omega=0.8, precision="fp64", cg="standard", max_batch=1, device="cuda",
+                 kv2=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
@@ -79,10 +82,10 @@ class Operator:
         self.N, self.nz, self.nlevels = int(N), int(nz), int(nlevels)
         self.ncol = 6 * self.N * self.N
         self.precision = precision
+        self.nine = kv2 is not None
         self.cfg = _lib.Config(self.N, self.nz, self.nlevels, n_pre, n_post, n_coarse,
                                float(omega), _lib.FP32 if precision == "fp32" else _lib.FP64,
-                               self._krylov(cg),
-                               int(max_batch))
+                               self._krylov(cg), int(max_batch), 9 if self.nine else 7)
         self.max_batch = int(max_batch)
         self.cg = cg
         nbytes = self.lib.helmholtz_workspace_bytes(ctypes.byref(self.cfg))
@@ -97,12 +100,16 @@ class Operator:
         kh = _dev(kh, torch.float64, self.device, (2, self.nz, self.ncol))
         delta = _dev(delta, torch.float64, self.device, (self.nz, self.ncol))
         kv = _dev(kv, torch.float64, self.device, (self.nz - 1, self.ncol)) if self.nz > 1 else None
+        if self.nine and self.nz > 2:
+            kv2 = _dev(kv2, torch.float64, self.device, (self.nz - 2, self.ncol))
+        else:
+            kv2 = None
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            code = self.lib.helmholtz_create(
+            code = self.lib.helmholtz_create9(
                 ctypes.byref(self.cfg), kh.data_ptr(), kv.data_ptr() if kv is not None else None,
-                delta.data_ptr(), self._ws_ptr, nbytes, _stream_ptr(self.device),
-                ctypes.byref(handle))
+                kv2.data_ptr() if kv2 is not None else None, delta.data_ptr(), self._ws_ptr,
+                nbytes, _stream_ptr(self.device), ctypes.byref(handle))
         _lib.check(code, "helmholtz_create")
         self._h = handle
 
@@ -181,15 +188,21 @@ class Operator:
         return ms.value, n.value, by.value
 
     def face_grad(self, lam, x):
-        """Coefficient gradients of L = g . x given lam = H^-1 g, summed over the batch."""
+        """Coefficient gradients of L = g . x given lam = H^-1 g, summed over the batch:
+        ``(g_kh, g_kv, g_delta)``, plus ``g_kv2`` last for the 9-cell stencil."""
         lam, _ = self._vec(lam)
         x, _ = self._vec(x)
         gkh = torch.empty((2, self.nz, self.ncol), dtype=torch.float64, device=self.device)
         gkv = torch.empty((max(self.nz - 1, 0), self.ncol), dtype=torch.float64,
                           device=self.device)
         gdl = torch.empty((self.nz, self.ncol), dtype=torch.float64, device=self.device)
-        _lib.check(self.lib.helmholtz_face_grad(
+        gkv2 = torch.empty((max(self.nz - 2, 0), self.ncol), dtype=torch.float64,
+                           device=self.device) if self.nine else None
+        _lib.check(self.lib.helmholtz_face_grad9(
             self._h, lam.data_ptr(), x.data_ptr(), lam.shape[0], gkh.data_ptr(),
-            gkv.data_ptr() if self.nz > 1 else None, gdl.data_ptr(), _stream_ptr(self.device)),
-            "helmholtz_face_grad")
+            gkv.data_ptr() if self.nz > 1 else None,
+            gkv2.data_ptr() if gkv2 is not None and self.nz > 2 else None, gdl.data_ptr(),
+            _stream_ptr(self.device)), "helmholtz_face_grad")
+        if self.nine:
+            return gkh, gkv, gdl, gkv2
         return gkh, gkv, gdl

@@ -1,0 +1,107 @@
+"""GPU parity for the 9-cell stencil (Section 3.5: couplings two levels apart;
+the smoother's column matrix drops them, Section 3.6) against the oracle.
+
+Bars as for the 7-point operator: float64 applies 1e-12 and V-cycles 1e-10
+relative (max abs difference over max abs value), float32 V-cycles within a
+float32 rounding bound, solves within +-1 iteration of the oracle, gradients
+1e-10.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import adjoint, helmholtz, krylov, mesh, multigrid
+from oracle.multigrid import MGParams
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(N, nz, L, w_h=1.0, w_v=100.0, w_v2=1.0, graded=False, precision="fp64", batch=1,
+           cg="standard", prm=MGParams()):
+    from paper_2002_00756_amd import Operator
+    kh, kv, delta = workloads.coefficients(N, nz, w_h, w_v, graded)
+    kv2 = workloads.next_nearest(N, nz, w_v2, graded)
+    levels, parents, childs = mesh.hierarchy(N, L)
+    hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta, kv2=kv2)
+    op = Operator(N, nz, kh, kv, delta, L, prm.n_pre, prm.n_post, prm.n_coarse, prm.omega,
+                  precision, cg, max_batch=batch, kv2=kv2 if nz > 2 else np.zeros((0, 6 * N * N)))
+    return hier, op
+
+
+def _rel(a, ref):
+    a = a.detach().cpu().numpy() if isinstance(a, torch.Tensor) else a
+    return float(np.abs(a - ref).max() / max(np.abs(ref).max(), 1e-300))
+
+
+CASES = [
+    # N, nz, L, w_h, w_v, w_v2, graded
+    (12, 10, 3, 1.0, 100.0, 1.0, False),
+    (8, 3, 2, 1.0, 100.0, 5.0, False),
+    (4, 5, 3, 5.0, 1000.0, 40.0, False),
+    (24, 30, 4, 1.0, 1000.0, 10.0, True),
+    (6, 70, 2, 1.0, 1000.0, 10.0, True),
+    (16, 120, 5, 2.0, 10.0, 3.0, False),
+]
+
+
+@pytest.mark.parametrize("N,nz,L,w_h,w_v,w_v2,graded", CASES)
+def test_apply_and_vcycle_parity(N, nz, L, w_h, w_v, w_v2, graded):
+    print(f"9-cell apply/vcycle N={N} nz={nz} L={L}", flush=True)
+    hier, op = _setup(N, nz, L, w_h, w_v, w_v2, graded, batch=2)
+    x = workloads.rhs(N, nz, 2, seed=7)
+    y = op.apply(torch.from_numpy(x).cuda())
+    assert _rel(y, hier.apply(0, x)) <= 1e-12
+    b = workloads.rhs(N, nz, 2, seed=8)
+    z = op.vcycle(torch.from_numpy(b).cuda())
+    assert _rel(z, multigrid.vcycle(hier, b)) <= 1e-10
+
+
+@pytest.mark.parametrize("N,nz,L", [(12, 10, 3), (24, 30, 4)])
+def test_vcycle_fp32(N, nz, L):
+    """Float32 V-cycle against the float64 oracle: a few float32 roundings per
+    sweep, amplified at most by the smoother's and the hierarchy's depth."""
+    hier, op = _setup(N, nz, L, w_v=1000.0, w_v2=10.0, graded=True, precision="fp32")
+    b = workloads.rhs(N, nz, seed=9)[0]
+    z = op.vcycle_f32(torch.from_numpy(b).float().cuda())
+    assert _rel(z.double(), multigrid.vcycle(hier, b)) <= 1e-4
+
+
+@pytest.mark.parametrize("cg", ["standard", "bicgstab"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_solve_matches_oracle(cg, precision):
+    w = workloads.C12x10_9
+    hier, op = _setup(w.N, w.nz, w.nlevels, w.w_h, w.w_v, w.w_v2, precision=precision, cg=cg)
+    b = workloads.rhs(w.N, w.nz)[0]
+    for rtol in (1e-6, 1e-10):
+        ref = krylov.solve(hier, b, rtol=rtol, method="bicgstab" if cg == "bicgstab" else "cg")
+        res = op.solve(torch.from_numpy(b).cuda(), rtol=rtol)
+        assert res.converged and abs(res.iters[0] - ref.iters) <= 1, (res.iters, ref.iters)
+        true = np.linalg.norm(b - hier.apply(0, res.x.cpu().numpy())) / np.linalg.norm(b)
+        assert true <= rtol * 1.05 + 1e-13
+
+
+def test_face_grad_with_kv2():
+    N, nz, L = 12, 10, 3
+    hier, op = _setup(N, nz, L, w_v2=2.0, batch=2)
+    lam = workloads.rhs(N, nz, 2, seed=3)
+    x = workloads.rhs(N, nz, 2, seed=4)
+    gkh, gkv, gdl, gkv2 = op.face_grad(torch.from_numpy(lam).cuda(), torch.from_numpy(x).cuda())
+    rkh, rkv, rdl = adjoint.face_gradients(hier.levels[0], lam, x)
+    rkv2 = adjoint.kv2_gradient(lam, x)
+    for a, r in ((gkh, rkh), (gkv, rkv), (gdl, rdl), (gkv2, rkv2)):
+        assert _rel(a, r) <= 1e-12
+
+
+def test_shallow_columns_reduce_to_seven_point():
+    """nz <= 2 has no couplings two levels apart: the 9-cell handle equals the
+    7-point one."""
+    from paper_2002_00756_amd import Operator
+    N, nz, L = 8, 2, 2
+    kh, kv, delta = workloads.coefficients(N, nz, 1.0, 100.0, False)
+    op9 = Operator(N, nz, kh, kv, delta, L, kv2=np.zeros((0, 6 * N * N)))
+    op7 = Operator(N, nz, kh, kv, delta, L)
+    b = torch.from_numpy(workloads.rhs(N, nz)[0]).cuda()
+    assert torch.equal(op9.vcycle(b), op7.vcycle(b))
+    r9, r7 = op9.solve(b, rtol=1e-10), op7.solve(b, rtol=1e-10)
+    assert r9.iters == r7.iters and torch.equal(r9.x, r7.x)
