@@ -253,6 +253,49 @@ def solver_comparison(Operator, torch, dev, reps=5):
             "table1": table1, "cfl_robustness": robust}
 
 
+def nine_cell_leg(Operator, torch, dev, _lib, steps=10, warmup=2):
+    """The 9-cell stencil of Section 3.5 on the benchmark shape (C192x70_9: the
+    C192x70 operator plus couplings two levels apart, 1 % of the nearest
+    ones): float32 V-cycle in float64 CG to 1e-6, the smoother dropping the
+    k+-2 couplings from its column solve. Sweep and apply GB/s count the extra
+    coefficient word (8 and 7 words per unknown)."""
+    w = workloads.C192x70_9
+    kh, kv, delta = workloads.workload_coefficients(w)
+    kv2 = workloads.workload_kv2(w)
+    op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", device=dev, kv2=kv2)
+    b = torch.from_numpy(workloads.rhs(w.N, w.nz)[0]).to(dev)
+    for _ in range(warmup):
+        op.solve(b, rtol=1e-6)
+    torch.cuda.synchronize()
+    op.profile(True)
+    t = time.perf_counter()
+    for _ in range(steps):
+        res = op.solve(b, rtol=1e-6)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / steps * 1e3
+    sw_ms, sw_n, sw_b = op.profile_read(_lib.PROF_SWEEP_FINE)
+    ap_ms, ap_n, ap_b = op.profile_read(_lib.PROF_APPLY_FINE)
+    op.profile(False)
+    true = float(torch.linalg.norm(b - op.apply(res.x)) / torch.linalg.norm(b))
+    b32 = b.float()
+    for _ in range(3):
+        op.vcycle_f32(b32)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(20):
+        op.vcycle_f32(b32)
+    torch.cuda.synchronize()
+    vc_ms = (time.perf_counter() - t) / 20 * 1e3
+    return {
+        "workload": f"{w.name} ({w.n} unknowns, w_v2 = {w.w_v2})",
+        "solves_per_s": 1e3 / ms, "ms_per_solve": ms, "iters": res.iters[0],
+        "true_relres": true, "vcycle_f32_ms": vc_ms,
+        "sweep_fine_us": sw_ms / max(sw_n, 1) * 1e3,
+        "sweep_fine_GBps": sw_b / (sw_ms * 1e-3) / 1e9 if sw_n else None,
+        "apply_fine_GBps": ap_b / (ap_ms * 1e-3) / 1e9 if ap_n else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +307,8 @@ def main():
     ap.add_argument("--no-batch-leg", action="store_true",
                     help="skip the C384x70 batch-of-4 forward+adjoint measurement")
     ap.add_argument("--cg", default="standard", choices=["standard", "flexible"])
+    ap.add_argument("--no-nine-cell", action="store_true",
+                    help="skip the 9-cell stencil measurement")
     ap.add_argument("--no-solver-comparison", action="store_true",
                     help="skip the pressure-solver configurations of Section 5.1 and the "
                          "CFL robustness study")
@@ -460,6 +505,8 @@ def main():
         out["batch4_C384x70"] = batch_leg(Operator, torch, dev)
     if not args.no_solver_comparison and args.workload == "C192x70":
         out["solver_comparison"] = solver_comparison(Operator, torch, dev)
+    if not args.no_nine_cell and args.workload == "C192x70":
+        out["nine_cell_C192x70"] = nine_cell_leg(Operator, torch, dev, _lib)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, kh, kv, delta, b_np, int(round(it64)))
     print(json.dumps(out), flush=True)
