@@ -39,3 +39,22 @@ def kv2_gradient(lam, x):
     lam = lam.reshape((-1,) + lam.shape[-2:])
     x = x.reshape((-1,) + x.shape[-2:])
     return -((lam[:, :-2] - lam[:, 2:]) * (x[:, :-2] - x[:, 2:])).sum(axis=0)
+
+
+def weighted_gradients(level, kh, kv, s, lam, x):
+    """Gradients for the row-weighted operator H = delta + S L (S = diag(s)),
+    with lam = H^-T g: since dH/dK = S a a^T for a face vector a = e_i - e_j,
+      dL/dK = -(s_i lam_i - s_j lam_j)(x_i - x_j),
+      dL/ds = -lam * (L x),   dL/d delta = -lam * x.
+    Returns ``(g_kh, g_kv, g_delta, g_s)``, summed over the batch."""
+    from .helmholtz import laplacian
+    lam = lam.reshape((-1,) + lam.shape[-2:])
+    x = x.reshape((-1,) + x.shape[-2:])
+    sl = s * lam
+    g_kh = np.stack([
+        -((sl - sl[..., level.nbr[d]]) * (x - x[..., level.nbr[d]])).sum(axis=0)
+        for d in (E, N_)])
+    g_kv = -((sl[:, :-1] - sl[:, 1:]) * (x[:, :-1] - x[:, 1:])).sum(axis=0)
+    g_delta = -(lam * x).sum(axis=0)
+    g_s = -(lam * laplacian(level, kh, kv, x)).sum(axis=0)
+    return g_kh, g_kv, g_delta, g_s

@@ -36,6 +36,7 @@ SEED_B = 1
 SEED_G = 2
 SEED_FD = 3
 SEED_K2 = 4
+SEED_S = 5
 
 
 @dataclasses.dataclass(frozen=True)
@@ -111,6 +112,13 @@ def next_nearest(N: int, nz: int, w_v2: float, graded: bool = False, seed: int =
     if graded:
         grade = np.exp(-np.arange(m, dtype=np.float64) / 20.0)
     return w_v2 * grade[:, None] * (1.0 + 0.1 * u)
+
+
+def row_weights(N: int, nz: int, seed: int = SEED_S):
+    """``s[nz][ncol] ~ U[0.5, 1.5]``: the per-cell row weight of the
+    non-symmetric operator H = delta + diag(s) L (the role of 1/rho*)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.5, 1.5, size=(nz, 6 * N * N))
 
 
 def workload_kv2(w: Workload):
