@@ -90,6 +90,9 @@ typedef struct {
     int32_t max_batch;    /* largest batch any call will pass, >= 1                          */
     int32_t stencil;      /* 7 (or 0): nearest vertical couplings only; 9: also couplings two
                              levels apart (Section 3.5), created with helmholtz_create9     */
+    int32_t weighted;     /* 0: symmetric H; 1: row-weighted, non-symmetric H = delta + S L,
+                             created with helmholtz_create_weighted (needs
+                             HELMHOLTZ_BICGSTAB and the 7-point stencil)                    */
 } helmholtz_config;
 
 /* Bytes of device workspace that helmholtz_create needs for cfg; 0 if cfg is
@@ -125,6 +128,24 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
 int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const double* kv,
                       const double* kv2, const double* delta, void* workspace,
                       size_t workspace_bytes, helmholtz_stream_t stream, helmholtz_t* out);
+
+/* The non-symmetric operator of Section 5.1: the paper's horizontal term acts
+ * like -(1/rho*) div(rho* theta* grad), a symmetric face-weighted Laplacian
+ * scaled row by row (Eq. continuum_pressure_operator). With a row weight s
+ * (the role of 1/rho*):
+ *   (H x)[k,c] = delta[k,c] x[k,c] + s[k,c] (L x)[k,c],   L x = the flux terms
+ * of helmholtz_create's operator, so the two cells of a face see different
+ * couplings and CG does not apply (cfg->cg_variant must be HELMHOLTZ_BICGSTAB,
+ * cfg->weighted 1, stencil 7). The column matrix of the smoother is the
+ * column part of H (rows weighted the same way); coarse levels take the mean
+ * of the four children's s. The adjoint calls below use H^T = delta + L S
+ * with the transposed V-cycle (the transpose of the V-cycle of H).
+ *   s     [nz][ncol]   > 0
+ * Other arguments as for helmholtz_create. */
+int helmholtz_create_weighted(const helmholtz_config* cfg, const double* kh, const double* kv,
+                              const double* delta, const double* s, void* workspace,
+                              size_t workspace_bytes, helmholtz_stream_t stream,
+                              helmholtz_t* out);
 
 /* Release host state (handle, pinned scalars). Never touches the workspace. */
 int helmholtz_destroy(helmholtz_t h);
@@ -184,6 +205,31 @@ int helmholtz_face_grad(helmholtz_t h, const double* lam, const double* x, int32
 int helmholtz_face_grad9(helmholtz_t h, const double* lam, const double* x, int32_t batch,
                          double* g_kh, double* g_kv, double* g_kv2, double* g_delta,
                          helmholtz_stream_t stream);
+
+/* Adjoint counterparts, for the gradient of a loss of x = H^-1 b: y = H^T x;
+ * one V-cycle of the transposed hierarchy; the solve of H^T lam = g (same
+ * Krylov method and preconditioner settings as helmholtz_solve). On a
+ * symmetric handle they are helmholtz_apply / _vcycle / _solve. Arguments,
+ * layouts and stream behaviour as for those calls. */
+int helmholtz_apply_adjoint(helmholtz_t h, const double* x, double* y, int32_t batch,
+                            helmholtz_stream_t stream);
+int helmholtz_vcycle_adjoint(helmholtz_t h, const double* b, double* x, int32_t batch,
+                             helmholtz_stream_t stream);
+int helmholtz_solve_adjoint(helmholtz_t h, const double* g, double* lam, int32_t batch,
+                            double rtol, int32_t maxiter, int32_t* iters, double* relres,
+                            helmholtz_stream_t stream);
+
+/* Coefficient gradients of L = g . x for a weighted handle, given
+ * lam = H^-T g and x, summed over the batch (dH/dK = S a a^T for a face
+ * vector a = e_i - e_j):
+ *   g_kh[s][k][c] = -sum_b (s lam[k,c] - s lam[k,n]) (x[k,c] - x[k,n]), n the E/N neighbour
+ *   g_kv[k][c]    = -sum_b (s lam[k,c] - s lam[k+1,c]) (x[k,c] - x[k+1,c])
+ *   g_delta       = -sum_b lam x,   g_s = -sum_b lam (L x)
+ * (each s at the cell of the lam it multiplies). Output layouts as for
+ * helmholtz_face_grad, g_s [nz][ncol]; all overwritten. Asynchronous. */
+int helmholtz_face_grad_weighted(helmholtz_t h, const double* lam, const double* x,
+                                 int32_t batch, double* g_kh, double* g_kv, double* g_delta,
+                                 double* g_s, helmholtz_stream_t stream);
 
 /* Mesh tables of C<N> as built by the library (host arrays, int32):
  *   nbr    [4][6N^2]  neighbour column in directions E, W, N, S

@@ -30,7 +30,8 @@ class Config(ctypes.Structure):
                 ("n_pre", ctypes.c_int32), ("n_post", ctypes.c_int32),
                 ("n_coarse", ctypes.c_int32), ("omega", ctypes.c_double),
                 ("mg_precision", ctypes.c_int32), ("cg_variant", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32), ("stencil", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("stencil", ctypes.c_int32),
+                ("weighted", ctypes.c_int32)]
 
 
 SIGNATURES = {
@@ -39,11 +40,19 @@ SIGNATURES = {
                                   ctypes.POINTER(_vp)]),
     "helmholtz_create9": (_c_int, [ctypes.POINTER(Config), _dp, _dp, _dp, _dp, _vp, _c_size,
                                    _vp, ctypes.POINTER(_vp)]),
+    "helmholtz_create_weighted": (_c_int, [ctypes.POINTER(Config), _dp, _dp, _dp, _dp, _vp,
+                                           _c_size, _vp, ctypes.POINTER(_vp)]),
     "helmholtz_destroy": (_c_int, [_vp]),
+    "helmholtz_apply_adjoint": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
+    "helmholtz_vcycle_adjoint": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
+    "helmholtz_face_grad_weighted": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _dp, _dp, _dp, _dp,
+                                              _vp]),
     "helmholtz_apply": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_vcycle": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_vcycle_f32": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_solve": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                 _i32p, _f64p, _vp]),
+    "helmholtz_solve_adjoint": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                  _i32p, _f64p, _vp]),
     "helmholtz_face_grad": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _dp, _dp, _dp, _vp]),
     "helmholtz_face_grad9": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _dp, _dp, _dp, _dp, _vp]),

@@ -34,6 +34,7 @@ struct LevelData {
     T* cc = nullptr;  // [nvp]
     T* mm = nullptr;  // [nvp]
     T* kv2 = nullptr; // [nvp]     9-cell stencil only
+    T* s = nullptr;   // [nvp]     weighted operator only: row weight
     T* b = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
     T* x = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
     T* t = nullptr;   // [B][nvp]   ping-pong partner of x
@@ -78,6 +79,9 @@ bool config_ok(const helmholtz_config* c) {
         return false;
     if (c->max_batch < 1) return false;
     if (c->stencil != 0 && c->stencil != 7 && c->stencil != 9) return false;
+    if (c->weighted != 0 && c->weighted != 1) return false;
+    // the weighted operator is not symmetric: BiCGStab, 7-point stencil
+    if (c->weighted && (c->cg_variant != HELMHOLTZ_BICGSTAB || c->stencil == 9)) return false;
     return true;
 }
 
@@ -98,6 +102,8 @@ struct helmholtz_s {
     helmholtz_config cfg{};
     int L = 0, nz = 0, B = 0;
     bool nine = false;  // 9-cell stencil (next-to-nearest vertical couplings)
+    bool weighted = false;  // row-weighted operator H = delta + S L
+    bool adj = false;       // the current call works with H^T (weighted handles)
     int64_t n = 0;    // unknowns per right-hand side on the finest level
     int64_t nvp = 0;  // tiled length of a finest-level vector (n plus padding)
     std::vector<Level> lev;
@@ -163,6 +169,10 @@ void layout(helmholtz_s* h, Carver& cv) {
             v.d.kv2 = cv.take<double>(nv);
             v.f.kv2 = cv.take<float>(nv);
         }
+        if (h->weighted) {
+            v.d.s = cv.take<double>(nv);
+            v.f.s = cv.take<float>(nv);
+        }
         if (l > 0) {
             v.d.b = cv.take<double>(size_t(B) * nv);
             v.d.x = cv.take<double>(size_t(B) * nv);
@@ -200,6 +210,7 @@ void init_shape(helmholtz_s* h, const helmholtz_config* cfg) {
     h->nz = cfg->nz;
     h->B = cfg->max_batch;
     h->nine = cfg->stencil == 9;
+    h->weighted = cfg->weighted == 1;
     h->lev.assign(h->L, Level{});
     for (int l = 0; l < h->L; ++l) {
         Level& v = h->lev[l];
@@ -279,7 +290,7 @@ LevelView<T> view(const helmholtz_s* h, int l) {
         else return v.f;
     }();
     return LevelView<T>{v.ncol, h->nz, v.nvp, v.nbr, v.fface, d.kh, d.kv, d.dl, d.cc, d.mm,
-                        d.kv2};
+                        d.kv2, d.s};
 }
 
 template <typename T>
@@ -291,7 +302,7 @@ LevelData<T>& data(helmholtz_s* h, int l) {
 // ---- sweep launch: compile-time bound on levels per thread ---------------
 inline int sweep_mid(int nz) { return nz / 2; }
 
-template <typename T, int JMAX, int MODE, int TC>
+template <typename T, int JMAX, int MODE, int TC, bool VARIANTS>
 void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
                     int batch, const int* active, hipStream_t s) {
     const Level& v = h->lev[l];
@@ -305,10 +316,16 @@ void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T
                            view<T>(h, l), b, x, xc, par, nvp_c, y, T(h->cfg.omega), batch, active,
                            sweep_mid(h->nz));
     };
-    if (h->nine)
-        go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, true>);
-    else
+    if constexpr (VARIANTS) {
+        if (h->weighted && h->adj)
+            go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowWT>);
+        else if (h->weighted)
+            go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowW>);
+        else
+            go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, true>);
+    } else {
         go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false>);
+    }
     if (prof)  // b, x, kh[2], cc, mm (, kv2) read; x_new written
         prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE,
                  (h->nine ? 8.0 : 7.0) * sizeof(T) * double(batch) * h->nz * v.ncol, s);
@@ -323,17 +340,26 @@ void launch_sweep_tc(const helmholtz_s* h, int l, const T* b, const T* x, const 
                      int batch, const int* active, hipStream_t s) {
     constexpr int KG = kBlock / TC;
     const int jn = (h->nz + KG - 1) / KG;
-#define HH_SWEEP_BUCKET(J)                                                    \
-    if (jn <= J) {                                                            \
-        launch_sweep_b<T, J, MODE, TC>(h, l, b, x, xc, y, batch, active, s);  \
-        return;                                                               \
+#define HH_SWEEP_BUCKET(J, V)                                                    \
+    if (jn <= J) {                                                               \
+        launch_sweep_b<T, J, MODE, TC, V>(h, l, b, x, xc, y, batch, active, s);  \
+        return;                                                                  \
     }
-    HH_SWEEP_BUCKET(1)
-    HH_SWEEP_BUCKET(2)
-    HH_SWEEP_BUCKET(4)
+    if (h->nine || h->weighted) {
+        // the 9-cell and weighted operators: fewer compiled bucket sizes
+        HH_SWEEP_BUCKET(4, true)
+        if (TC == 32) {
+            HH_SWEEP_BUCKET(9, true)
+            HH_SWEEP_BUCKET(15, true)
+        }
+        return;
+    }
+    HH_SWEEP_BUCKET(1, false)
+    HH_SWEEP_BUCKET(2, false)
+    HH_SWEEP_BUCKET(4, false)
     if (TC == 32) {
-        HH_SWEEP_BUCKET(9)
-        HH_SWEEP_BUCKET(15)
+        HH_SWEEP_BUCKET(9, false)
+        HH_SWEEP_BUCKET(15, false)
     }
 #undef HH_SWEEP_BUCKET
 }
@@ -386,6 +412,12 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
     } else if (h->nine) {
         if (pair) go(k_resid_restrict<T, false, true, true>);
         else go(k_resid_restrict<T, false, false, true>);
+    } else if (h->weighted && h->adj) {
+        if (pair) go(k_resid_restrict<T, false, true, false, kRowWT>);
+        else go(k_resid_restrict<T, false, false, false, kRowWT>);
+    } else if (h->weighted) {
+        if (pair) go(k_resid_restrict<T, false, true, false, kRowW>);
+        else go(k_resid_restrict<T, false, false, false, kRowW>);
     } else {
         if (pair) go(k_resid_restrict<T, false, true>);
         else go(k_resid_restrict<T, false, false>);
@@ -404,7 +436,23 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
         hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), x, y, w, batch, nkc,
                            cg_state(h), active);
     };
-    if (h->nine) {
+    if (h->weighted) {
+        if (h->adj) {
+            switch (dot) {
+                case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, false, kRowWT>); break;
+                case kDotWY: go(k_apply<T, kDotWY, kApplyChunk, false, kRowWT>); break;
+                case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk, false, kRowWT>); break;
+                default: go(k_apply<T, kDotNone, kApplyChunk, false, kRowWT>); break;
+            }
+        } else {
+            switch (dot) {
+                case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, false, kRowW>); break;
+                case kDotWY: go(k_apply<T, kDotWY, kApplyChunk, false, kRowW>); break;
+                case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk, false, kRowW>); break;
+                default: go(k_apply<T, kDotNone, kApplyChunk, false, kRowW>); break;
+            }
+        }
+    } else if (h->nine) {
         switch (dot) {
             case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, true>); break;
             case kDotWY: go(k_apply<T, kDotWY, kApplyChunk, true>); break;
@@ -625,6 +673,18 @@ int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
     return broke ? HELMHOLTZ_NOT_CONVERGED : HELMHOLTZ_OK;
 }
 
+int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
+                const double* kv2, const double* delta, const double* sw, void* workspace,
+                size_t workspace_bytes, helmholtz_stream_t stream_, helmholtz_t* out);
+
+// Weighted handles run the calls that take H^T with the transposed kernels.
+struct AdjointScope {
+    helmholtz_s* h;
+    bool old;
+    explicit AdjointScope(helmholtz_s* h_) : h(h_), old(h_->adj) { h->adj = h->weighted; }
+    ~AdjointScope() { h->adj = old; }
+};
+
 }  // namespace
 
 // ===========================================================================
@@ -666,9 +726,9 @@ int helmholtz_create(const helmholtz_config* cfg, const double* kh, const double
                      helmholtz_stream_t stream_, helmholtz_t* out) {
     if (!out) return HELMHOLTZ_EINVAL;
     *out = nullptr;
-    if (config_ok(cfg) && cfg->stencil == 9) return HELMHOLTZ_EINVAL;  // needs kv2
-    return helmholtz_create9(cfg, kh, kv, nullptr, delta, workspace, workspace_bytes, stream_,
-                             out);
+    if (config_ok(cfg) && (cfg->stencil == 9 || cfg->weighted)) return HELMHOLTZ_EINVAL;
+    return create_impl(cfg, kh, kv, nullptr, delta, nullptr, workspace, workspace_bytes, stream_,
+                       out);
 }
 
 int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const double* kv,
@@ -676,11 +736,35 @@ int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const doubl
                       size_t workspace_bytes, helmholtz_stream_t stream_, helmholtz_t* out) {
     if (!out) return HELMHOLTZ_EINVAL;
     *out = nullptr;
+    if (config_ok(cfg) && cfg->weighted) return HELMHOLTZ_EINVAL;
+    return create_impl(cfg, kh, kv, kv2, delta, nullptr, workspace, workspace_bytes, stream_, out);
+}
+
+int helmholtz_create_weighted(const helmholtz_config* cfg, const double* kh, const double* kv,
+                              const double* delta, const double* s, void* workspace,
+                              size_t workspace_bytes, helmholtz_stream_t stream_,
+                              helmholtz_t* out) {
+    if (!out) return HELMHOLTZ_EINVAL;
+    *out = nullptr;
+    if (config_ok(cfg) && (!cfg->weighted || !s)) return HELMHOLTZ_EINVAL;
+    return create_impl(cfg, kh, kv, nullptr, delta, s, workspace, workspace_bytes, stream_, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
+                const double* kv2, const double* delta, const double* sw, void* workspace,
+                size_t workspace_bytes, helmholtz_stream_t stream_, helmholtz_t* out) {
+    if (!out) return HELMHOLTZ_EINVAL;
+    *out = nullptr;
     if (!config_ok(cfg)) return HELMHOLTZ_EINVAL;
     if (int e = shape_error(cfg)) return e;
     if (!kh || !delta || (cfg->nz > 1 && !kv)) return HELMHOLTZ_EINVAL;
     const bool nine = cfg->stencil == 9;
     if (nine != (kv2 != nullptr) && !(nine && cfg->nz <= 2)) return HELMHOLTZ_EINVAL;
+    if ((cfg->weighted == 1) != (sw != nullptr)) return HELMHOLTZ_EINVAL;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % HELMHOLTZ_WORKSPACE_ALIGN))
         return HELMHOLTZ_EWORKSPACE;
     const size_t need = helmholtz_workspace_bytes(cfg);
@@ -761,16 +845,16 @@ int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const doubl
         Level& v = h->lev[0];
         const int64_t nv = int64_t(nz) * v.ncol;
         hipLaunchKernelGGL(k_setup_fine, dim3(grid_for(nv)), dim3(kBlock), 0, s, v.ncol, nz,
-                           v.nvp, kh, kv, delta, kv2, v.d.kh, v.d.kv, v.d.dl,
-                           kv2 ? v.d.kv2 : nullptr, h->flags);
+                           v.nvp, kh, kv, delta, kv2, sw, v.d.kh, v.d.kv, v.d.dl,
+                           kv2 ? v.d.kv2 : nullptr, sw ? v.d.s : nullptr, h->flags);
     }
     for (int l = 1; l < h->L; ++l) {
         Level& f = h->lev[l - 1];
         Level& c = h->lev[l];
         const int64_t nv = int64_t(nz) * c.ncol;
         hipLaunchKernelGGL(k_coarsen, dim3(grid_for(nv)), dim3(kBlock), 0, s, c.ncol, nz, f.nvp,
-                           c.nvp, c.child, f.d.kh, f.d.kv, f.d.dl, f.d.kv2, c.d.kh, c.d.kv,
-                           c.d.dl, c.d.kv2);
+                           c.nvp, c.child, f.d.kh, f.d.kv, f.d.dl, f.d.kv2, f.d.s, c.d.kh,
+                           c.d.kv, c.d.dl, c.d.kv2, c.d.s);
     }
     for (int l = 0; l < h->L; ++l) {
         Level& v = h->lev[l];
@@ -784,6 +868,7 @@ int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const doubl
         convert<double, float>(v.d.cc, v.f.cc, nv, s);
         convert<double, float>(v.d.mm, v.f.mm, nv, s);
         if (h->nine) convert<double, float>(v.d.kv2, v.f.kv2, nv, s);
+        if (h->weighted) convert<double, float>(v.d.s, v.f.s, nv, s);
     }
     if (last_error() != HELMHOLTZ_OK) return fail(HELMHOLTZ_EHIP);
     if (hipMemcpyAsync(h->hflags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -794,6 +879,10 @@ int helmholtz_create9(const helmholtz_config* cfg, const double* kh, const doubl
     *out = h;
     return HELMHOLTZ_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 int helmholtz_profile_enable(helmholtz_t h, int enable) {
     if (!h) return HELMHOLTZ_EINVAL;
@@ -997,12 +1086,50 @@ int helmholtz_face_grad9(helmholtz_t h, const double* lam, const double* x, int3
     if (int e = check_batch(h, batch)) return e;
     if (!lam || !x || !g_kh || !g_delta || (h->nz > 1 && !g_kv)) return HELMHOLTZ_EINVAL;
     if (g_kv2 && !h->nine) return HELMHOLTZ_EINVAL;
+    if (h->weighted) return HELMHOLTZ_EINVAL;  // helmholtz_face_grad_weighted
     const Level& v = h->lev[0];
     const int64_t total = int64_t(h->nz) * v.ncol;
     const int grid = int((total + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_face_grad, dim3(grid), dim3(kBlock), 0,
                        reinterpret_cast<hipStream_t>(stream), v.ncol, h->nz, v.nbr, lam, x, batch,
                        g_kh, g_kv, g_delta, h->nz > 2 ? g_kv2 : nullptr);
+    return last_error();
+}
+
+int helmholtz_apply_adjoint(helmholtz_t h, const double* x, double* y, int32_t batch,
+                            helmholtz_stream_t stream) {
+    if (!h) return HELMHOLTZ_EINVAL;
+    AdjointScope scope(h);
+    return helmholtz_apply(h, x, y, batch, stream);
+}
+
+int helmholtz_vcycle_adjoint(helmholtz_t h, const double* b, double* x, int32_t batch,
+                             helmholtz_stream_t stream) {
+    if (!h) return HELMHOLTZ_EINVAL;
+    AdjointScope scope(h);
+    return helmholtz_vcycle(h, b, x, batch, stream);
+}
+
+int helmholtz_solve_adjoint(helmholtz_t h, const double* g, double* lam, int32_t batch,
+                            double rtol, int32_t maxiter, int32_t* iters, double* relres,
+                            helmholtz_stream_t stream) {
+    if (!h) return HELMHOLTZ_EINVAL;
+    AdjointScope scope(h);
+    return helmholtz_solve(h, g, lam, batch, rtol, maxiter, iters, relres, stream);
+}
+
+int helmholtz_face_grad_weighted(helmholtz_t h, const double* lam, const double* x,
+                                 int32_t batch, double* g_kh, double* g_kv, double* g_delta,
+                                 double* g_s, helmholtz_stream_t stream) {
+    if (int e = check_batch(h, batch)) return e;
+    if (!h->weighted) return HELMHOLTZ_EINVAL;
+    if (!lam || !x || !g_kh || !g_delta || !g_s || (h->nz > 1 && !g_kv)) return HELMHOLTZ_EINVAL;
+    const Level& v = h->lev[0];
+    const int64_t total = int64_t(h->nz) * v.ncol;
+    const int grid = int((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_face_grad_w, dim3(grid), dim3(kBlock), 0,
+                       reinterpret_cast<hipStream_t>(stream), view<double>(h, 0), lam, x, batch,
+                       g_kh, g_kv, g_delta, g_s);
     return last_error();
 }
 

@@ -16,6 +16,8 @@
 //   dl (delta)     [nvp]
 //   kv2            [nvp]               9-cell stencil only: coupling of levels
 //                                      k and k+2; rows nz-2, nz-1 are zero
+//   s              [nvp]               weighted operator only: row weight of
+//                                      H = delta + S L (below)
 //   cc, mm         [nvp]               factors of the column operator (below)
 //   nbr            [4][ncol]           E, W, N, S neighbour column
 //   fface          [2][ncol]           offset in kh of the W and S face at
@@ -38,6 +40,11 @@
 // (e_{k-1} + kv_{k-1}), pivot p_k = e_k + kv_k. Stored: mm_k = 1/p_k and
 // cc_k = kv_k / p_k, so that forward elimination is t_k = r_k + cc_{k-1} t_{k-1}
 // and back substitution is z_k = mm_k t_k + cc_k z_{k+1}.
+// Weighted operator H = delta + S L (S = diag(s), L the flux terms): its column
+// matrix is S Hz' with Hz' = delta/s + (the column part of L) symmetric, so the
+// factors are those of Hz' (delta/s in place of delta) and the sweeps scale
+// by 1/s: forward, Hz^-1 (b + S sum K x_n) = Hz'^-1 (b/s + sum K x_n); for
+// H^T = delta + L S, Hz^-T (b + sum K s_n x_n) = S^-1 Hz'^-1 (b + sum K s_n x_n).
 // The smoother uses a "twisted" split at row mid = nz / 2: rows above mid
 // are factored top-down as above, rows below mid bottom-up (f_{nz-1} =
 // s_{nz-1}, f_k = s_k + kv_k f_{k+1} / (f_{k+1} + kv_k), q_k = f_k + kv_{k-1},
@@ -80,7 +87,12 @@ struct LevelView {
     const T* __restrict__ cc;
     const T* __restrict__ mm;
     const T* __restrict__ kv2;  // null for the 7-point stencil
+    const T* __restrict__ s;    // row weight; null for the symmetric operator
 };
+
+// Operator form a kernel is built for: symmetric, row-weighted H = delta + S L,
+// or its transpose H^T = delta + L S.
+enum { kSym = 0, kRowW = 1, kRowWT = 2 };
 
 // ---------------------------------------------------------------------------
 // Block-Jacobi sweep (Eq. jacobi):
@@ -229,7 +241,7 @@ struct SweepTile {
 };
 
 template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = kBlock,
-          int CH_ = 0, bool K2 = false>
+          int CH_ = 0, bool K2 = false, int SC = kSym>
 __global__ void __launch_bounds__(NT)
 k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         const T* __restrict__ xc, const int32_t* __restrict__ parent, int nvp_c,
@@ -238,6 +250,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     constexpr int BOT = (TC + 63) / 64 * 64;  // first lane of the bottom elimination (own wave)
     static_assert(BOT + TC <= NT, "two elimination lane groups must fit the workgroup");
     static_assert(kTile % TC == 0, "a sweep tile lies inside one storage tile");
+    static_assert(!(K2 && SC != kSym), "the weighted operator has the 7-point stencil");
     constexpr bool kHasX = MODE == kPlain || MODE == kProlong;
     constexpr bool kHasP = MODE == kProlong || MODE == kProlongZero;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -288,10 +301,12 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     // thread keeps several rows of independent loads in flight.
     constexpr int CH = CH_ > 0 ? CH_ : (MODE == kZero ? 8 : 2);
     T xo[JMAX], mo[JMAX];
+    T so[SC == kRowWT ? JMAX : 1];  // H^T: own weight, for z / s
 #pragma unroll
     for (int j0 = 0; j0 < JMAX; j0 += CH) {
         T vb[CH], vc[CH], vm[CH], vx[CH][5], vk[CH][4];
         T v2[CH];  // 9-cell: kv2_k x_{k+2} + kv2_{k-2} x_{k-2}
+        T vs[CH], vsn[CH][4];  // weighted: own weight, neighbours' weights (H^T)
 #pragma unroll
         for (int jj = 0; jj < CH; ++jj) {
             const int j = j0 + jj;
@@ -302,9 +317,13 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
 #pragma unroll
             for (int d = 0; d < 4; ++d) vk[jj][d] = T(0);
             v2[jj] = T(0);
+            vs[jj] = T(1);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) vsn[jj][d] = T(1);
             if (j < JMAX && k < nz && valid) {
                 const int o = ob + kTile * k;
                 vb[jj] = b[o];
+                if constexpr (SC != kSym) vs[jj] = L.s[o];
                 vc[jj] = L.cc[o];
                 vm[jj] = L.mm[o];
                 if (MODE != kZero) {
@@ -315,6 +334,10 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
 #pragma unroll
                     for (int d = 0; d < 4; ++d) vx[jj][d] = xv(k, nb[d], pn[d]);
                     vx[jj][4] = xv(k, ob, pn[4]);
+                    if constexpr (SC == kRowWT) {
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) vsn[jj][d] = L.s[nb[d] + kTile * k];
+                    }
                     if constexpr (K2) {
                         if (k + 2 < nz) v2[jj] = L.kv2[o] * xv(k + 2, ob, pn[4]);
                         if (k >= 2) v2[jj] += L.kv2[o - 2 * kTile] * xv(k - 2, ob, pn[4]);
@@ -328,9 +351,18 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
             const int k = kg + j * KG;
             if (j < JMAX && k < nz) {
                 T r = vb[jj];
-                if (MODE != kZero)
+                if constexpr (SC == kRowW) r = vb[jj] / vs[jj];
+                if constexpr (SC == kRowWT) {
+                    so[j] = vs[jj];
+                    if (MODE != kZero)
+                        r += vk[jj][0] * (vsn[jj][0] * vx[jj][0]) +
+                             vk[jj][1] * (vsn[jj][1] * vx[jj][1]) +
+                             vk[jj][2] * (vsn[jj][2] * vx[jj][2]) +
+                             vk[jj][3] * (vsn[jj][3] * vx[jj][3]);
+                } else if (MODE != kZero) {
                     r += vk[jj][0] * vx[jj][0] + vk[jj][1] * vx[jj][1] + vk[jj][2] * vx[jj][2] +
                          vk[jj][3] * vx[jj][3];
+                }
                 if (K2 && MODE != kZero) r += v2[jj];
                 xo[j] = vx[jj][4];
                 mo[j] = vm[jj];
@@ -350,7 +382,8 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     for (int j = 0; j < JMAX; ++j) {
         const int k = kg + j * KG;
         if (k < nz) {
-            const T z = R[k * TC + lc];
+            T z = R[k * TC + lc];
+            if constexpr (SC == kRowWT) z = z / so[j];
             y[ob + kTile * k] = (MODE == kZero) ? om * z : om1 * xo[j] + om * z;
         }
     }
@@ -525,7 +558,7 @@ k_finalize(CgState st, int mode, int cnt, int seq) {
 // kDotWYYY w . y and y . y (BiCGStab: (t, s), (t, t)). Partial sums per block.
 enum { kDotNone = 0, kDotXY = 1, kDotWY = 2, kDotWYYY = 3 };
 
-template <typename T, int DOT, int KC, bool K2 = false>
+template <typename T, int DOT, int KC, bool K2 = false, int SC = kSym>
 __global__ void __launch_bounds__(kBlock)
 k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
         int batch, int nkc, CgState st, const int* __restrict__ active) {
@@ -552,10 +585,15 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
         const int k0 = kc * KC;
         // all loads of the chunk are issued before any is used
         T xc[KC + 2], kvv[KC + 1], dl[KC], xn[KC][4], kh[KC][4];
+        // weighted: own weights (k0-1 .. k0+KC; H^T) or (k0 .. k0+KC-1; H),
+        // neighbours' weights (H^T)
+        T sc[KC + 2], sn[KC][4];
 #pragma unroll
         for (int j = 0; j < KC + 2; ++j) {
             const int k = k0 - 1 + j;
             xc[j] = (k >= 0 && k < nz) ? x[ob + kTile * k] : T(0);
+            sc[j] = T(1);
+            if (SC != kSym && k >= 0 && k < nz) sc[j] = L.s[ob + kTile * k];
         }
 #pragma unroll
         for (int j = 0; j < KC + 1; ++j) {
@@ -585,6 +623,8 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
                 dl[j] = L.dl[o];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) xn[j][d] = x[nb[d] + kTile * k];
+#pragma unroll
+                for (int d = 0; d < 4; ++d) sn[j][d] = SC == kRowWT ? L.s[nb[d] + kTile * k] : T(1);
                 kh[j][0] = L.kh[o];
                 kh[j][1] = L.kh[fW + uint32_t(kTile * k)];
                 kh[j][2] = khN[o];
@@ -597,10 +637,27 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
             if (k < nz) {
                 const T xo = xc[j + 1];
                 T v = dl[j] * xo;
+                if constexpr (SC == kRowWT) {
+                    // H^T x = delta x + L (s x)
+                    const T uo = sc[j + 1] * xo;
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) v += kh[j][d] * (uo - sn[j][d] * xn[j][d]);
+                    v += kvv[j + 1] * (uo - sc[j + 2] * xc[j + 2]);
+                    v += kvv[j] * (uo - sc[j] * xc[j]);
+                } else if constexpr (SC == kRowW) {
+                    // H x = delta x + s (L x)
+                    T f = T(0);
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) f += kh[j][d] * (xo - xn[j][d]);
+                    f += kvv[j + 1] * (xo - xc[j + 2]);
+                    f += kvv[j] * (xo - xc[j]);
+                    v += sc[j + 1] * f;
+                } else {
 #pragma unroll
                 for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
                 v += kvv[j + 1] * (xo - xc[j + 2]);
                 v += kvv[j] * (xo - xc[j]);
+                }
                 if constexpr (K2) {
                     // x[k-2] and x[k+2] (xc[i] holds x[k0-1+i])
                     const T xm2 = j >= 1 ? xc[j - 1] : xlo;
@@ -662,7 +719,7 @@ __device__ __forceinline__ void load_pair(const T* __restrict__ p, int64_t i, T&
     }
 }
 
-template <typename T, bool ZEROX, bool PAIR, bool K2 = false>
+template <typename T, bool ZEROX, bool PAIR, bool K2 = false, int SC = kSym>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
                  const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
@@ -715,16 +772,34 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
 #pragma unroll
         for (int f = 0; f < 8; ++f) out[f] = tile_base(out[f], nz);
     }
+    static_assert(!(K2 && SC != kSym), "the weighted operator has the 7-point stencil");
+    // H^T: the flux terms act on u = s x, so every x below is multiplied by its
+    // weight; H: each child's flux terms are weighted by its own s, so the
+    // fluxes between siblings no longer cancel and are evaluated too.
+    auto su = [&](T& v0, T& v1, int off) {
+        if constexpr (SC == kRowWT) {
+            T w0, w1;
+            load_pair<T, PAIR>(F.s, off, w0, w1);
+            v0 *= w0;
+            v1 *= w1;
+        }
+    };
     T xdn[4] = {T(0), T(0), T(0), T(0)}, xo[4], kvdn[4] = {T(0), T(0), T(0), T(0)};
     if (k0 > 0) {
         const int rdn = kTile * (k0 - 1);
         load_pair<T, PAIR>(x, rdn + cb[0], xdn[0], xdn[1]);
         load_pair<T, PAIR>(x, rdn + cb[2], xdn[2], xdn[3]);
+        su(xdn[0], xdn[1], rdn + cb[0]);
+        su(xdn[2], xdn[3], rdn + cb[2]);
         load_pair<T, PAIR>(F.kv, rdn + cb[0], kvdn[0], kvdn[1]);
         load_pair<T, PAIR>(F.kv, rdn + cb[2], kvdn[2], kvdn[3]);
     }
     load_pair<T, PAIR>(x, kTile * k0 + cb[0], xo[0], xo[1]);
     load_pair<T, PAIR>(x, kTile * k0 + cb[2], xo[2], xo[3]);
+    // (H^T: xo holds u = s x; the delta term needs x itself, kept in xr)
+    T xr[4] = {xo[0], xo[1], xo[2], xo[3]};
+    su(xo[0], xo[1], kTile * k0 + cb[0]);
+    su(xo[2], xo[3], kTile * k0 + cb[2]);
     // 9-cell: window x[k-2], kv2[k-2], kv2[k-1] of the four children
     T xm2[4] = {T(0), T(0), T(0), T(0)}, k2m2[4] = {T(0), T(0), T(0), T(0)};
     T k2m1[4] = {T(0), T(0), T(0), T(0)};
@@ -745,9 +820,16 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
     for (int k = k0; k < k1; ++k) {
         const int r = kTile * k;
         T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8];
+        T xupr[4] = {T(0), T(0), T(0), T(0)};  // H^T: raw x at k+1
         if (k + 1 < nz) {
             load_pair<T, PAIR>(x, r + kTile + cb[0], xup[0], xup[1]);
             load_pair<T, PAIR>(x, r + kTile + cb[2], xup[2], xup[3]);
+            if constexpr (SC == kRowWT) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) xupr[q] = xup[q];
+                su(xup[0], xup[1], r + kTile + cb[0]);
+                su(xup[2], xup[3], r + kTile + cb[2]);
+            }
         }
         load_pair<T, PAIR>(b, r + cb[0], vb[0], vb[1]);
         load_pair<T, PAIR>(b, r + cb[2], vb[2], vb[3]);
@@ -758,16 +840,41 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
 #pragma unroll
         for (int f = 0; f < 8; ++f) {
             vxo[f] = x[out[f] + r];
+            if constexpr (SC == kRowWT) vxo[f] *= F.s[out[f] + r];
             vk[f] = F.kh[fc[f] + uint32_t(r)];
         }
         T acc = ((vb[0] + vb[1]) + vb[2]) + vb[3];
+        if constexpr (SC == kRowW) {
+            // each child's flux row, with the four faces between siblings:
+            // c00|c10 and c01|c11 (E faces of c00, c01), c00|c01 and c10|c11
+            // (N faces of c00, c10)
+            T sw[4], iE0, iE1, iN0, iN1, unused;
+            load_pair<T, PAIR>(F.s, r + cb[0], sw[0], sw[1]);
+            load_pair<T, PAIR>(F.s, r + cb[2], sw[2], sw[3]);
+            load_pair<T, PAIR>(F.kh, r + cb[0], iE0, unused);
+            load_pair<T, PAIR>(F.kh, r + cb[2], iE1, unused);
+            load_pair<T, PAIR>(F.kh + nv, r + cb[0], iN0, iN1);
+            T Lr[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            acc -= vd[s] * xo[s];
-            acc -= vkv[s] * (xo[s] - xup[s]) + kvdn[s] * (xo[s] - xdn[s]);
+            for (int q = 0; q < 4; ++q)
+                Lr[q] = vkv[q] * (xo[q] - xup[q]) + kvdn[q] * (xo[q] - xdn[q]);
+#pragma unroll
+            for (int f = 0; f < 8; ++f) Lr[f >> 1] += vk[f] * (xo[f >> 1] - vxo[f]);
+            Lr[0] += iE0 * (xo[0] - xo[1]) + iN0 * (xo[0] - xo[2]);
+            Lr[1] += iE0 * (xo[1] - xo[0]) + iN1 * (xo[1] - xo[3]);
+            Lr[2] += iE1 * (xo[2] - xo[3]) + iN0 * (xo[2] - xo[0]);
+            Lr[3] += iE1 * (xo[3] - xo[2]) + iN1 * (xo[3] - xo[1]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc -= vd[q] * xo[q] + sw[q] * Lr[q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                acc -= vd[q] * (SC == kRowWT ? xr[q] : xo[q]);
+                acc -= vkv[q] * (xo[q] - xup[q]) + kvdn[q] * (xo[q] - xdn[q]);
+            }
+#pragma unroll
+            for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
         }
-#pragma unroll
-        for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
         T k2[4] = {T(0), T(0), T(0), T(0)};
         if constexpr (K2) {
             T xp2[4] = {T(0), T(0), T(0), T(0)};
@@ -791,6 +898,7 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
             }
             xdn[s] = xo[s];
             xo[s] = xup[s];
+            if constexpr (SC == kRowWT) xr[s] = xupr[s];
             kvdn[s] = vkv[s];
         }
     }
@@ -821,8 +929,9 @@ k_prolong(int ncol, int nz, int nvp, int nvp_c, const int32_t* __restrict__ pare
 __global__ void __launch_bounds__(kBlock)
 k_setup_fine(int ncol, int nz, int nvp, const double* __restrict__ kh_in,
              const double* __restrict__ kv_in, const double* __restrict__ dl_in,
-             const double* __restrict__ kv2_in, double* __restrict__ kh, double* __restrict__ kv,
-             double* __restrict__ dl, double* __restrict__ kv2, int* __restrict__ flags) {
+             const double* __restrict__ kv2_in, const double* __restrict__ s_in,
+             double* __restrict__ kh, double* __restrict__ kv, double* __restrict__ dl,
+             double* __restrict__ kv2, double* __restrict__ sw, int* __restrict__ flags) {
     const int64_t total = int64_t(nz) * ncol;
     int bad = 0;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
@@ -844,6 +953,12 @@ k_setup_fine(int ncol, int nz, int nvp, const double* __restrict__ kh_in,
             if (!isfinite(v2)) bad |= 1;
             if (!(v2 >= 0.0)) bad |= 2;
         }
+        if (sw) {
+            const double w = s_in[i];
+            sw[o] = w;
+            if (!isfinite(w)) bad |= 1;
+            if (!(w > 0.0)) bad |= 2;
+        }
     }
     if (bad) atomicOr(flags, bad);
 }
@@ -855,8 +970,8 @@ __global__ void __launch_bounds__(kBlock)
 k_coarsen(int ncol_c, int nz, int nvp_f, int nvp_c, const int32_t* __restrict__ child,
           const double* __restrict__ khf, const double* __restrict__ kvf,
           const double* __restrict__ dlf, const double* __restrict__ kv2f,
-          double* __restrict__ khc, double* __restrict__ kvc, double* __restrict__ dlc,
-          double* __restrict__ kv2c) {
+          const double* __restrict__ sf, double* __restrict__ khc, double* __restrict__ kvc,
+          double* __restrict__ dlc, double* __restrict__ kv2c, double* __restrict__ sc) {
     const int64_t total = int64_t(nz) * ncol_c;
     for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < total;
          i += int64_t(gridDim.x) * kBlock) {
@@ -873,6 +988,8 @@ k_coarsen(int ncol_c, int nz, int nvp_f, int nvp_c, const int32_t* __restrict__ 
         kvc[o] = ((kvf[c00] + kvf[c10]) + kvf[c01]) + kvf[c11];
         dlc[o] = ((dlf[c00] + dlf[c10]) + dlf[c01]) + dlf[c11];
         if (kv2c) kv2c[o] = ((kv2f[c00] + kv2f[c10]) + kv2f[c01]) + kv2f[c11];
+        // row weight (a pointwise field): mean of the four children
+        if (sc) sc[o] = 0.25 * (((sf[c00] + sf[c10]) + sf[c01]) + sf[c11]);
     }
 }
 
@@ -887,8 +1004,9 @@ k_factor(LevelView<double> L, int mid, double* __restrict__ cc, double* __restri
     const double* khN = L.kh + L.nvp;
     auto s_of = [&](int k) {
         const int o = ob + kTile * k;
-        double v = L.dl[o] + L.kh[o] + L.kh[fW + uint32_t(kTile * k)] + khN[o] +
-                   L.kh[fS + uint32_t(kTile * k)];
+        // weighted operator: the factors are those of Hz' (delta / s)
+        double v = (L.s ? L.dl[o] / L.s[o] : L.dl[o]) + L.kh[o] + L.kh[fW + uint32_t(kTile * k)] +
+                   khN[o] + L.kh[fS + uint32_t(kTile * k)];
         // 9-cell: the dropped couplings two levels apart stay in the diagonal
         if (L.kv2) v += L.kv2[o] + (k >= 2 ? L.kv2[o - 2 * kTile] : 0.0);
         return v;
@@ -1084,6 +1202,62 @@ k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
         const double zv = double(z[off + i]);
         p[off + i] = init ? zv : zv + beta * p[off + i];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Gradients for the weighted operator H = delta + S L given lam = H^-T g (ABI
+// layout, summed over the batch): dH/dK = S a a^T for a face vector a, so
+//   g_kh = -(s_c lam_c - s_n lam_n)(x_c - x_n) (E, N faces), g_kv likewise
+//   along k, g_delta = -lam x, g_s = -lam (L x).
+// Reads the finest level's float64 coefficients and weights (tiled).
+__global__ void __launch_bounds__(kBlock)
+k_face_grad_w(LevelView<double> L, const double* __restrict__ lam, const double* __restrict__ x,
+              int batch, double* __restrict__ gkh, double* __restrict__ gkv,
+              double* __restrict__ gdl, double* __restrict__ gs) {
+    const int ncol = L.ncol, nz = L.nz;
+    const int64_t total = int64_t(nz) * ncol;
+    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = int64_t(lb) * kBlock + threadIdx.x;
+    if (i >= total) return;
+    const int k = int(i / ncol);
+    const int c = int(i % ncol);
+    int nbc[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) nbc[d] = L.nbr[d * ncol + c];
+    const int o = tile_base(c, nz) + kTile * k;
+    const double* khN = L.kh + L.nvp;
+    // couplings of the four faces of c (E, W, N, S) and the vertical ones
+    const double K[4] = {L.kh[o], L.kh[L.fface[c] + uint32_t(kTile * k)], khN[o],
+                         L.kh[L.fface[ncol + c] + uint32_t(kTile * k)]};
+    const double kup = L.kv[o], kdn = k > 0 ? L.kv[o - kTile] : 0.0;
+    const double sc = L.s[o];
+    const double se = L.s[tile_base(nbc[0], nz) + kTile * k];
+    const double sn = L.s[tile_base(nbc[2], nz) + kTile * k];
+    const double su = k + 1 < nz ? L.s[o + kTile] : 0.0;
+    const int64_t row = int64_t(k) * ncol;
+    double ge = 0.0, gn = 0.0, gv = 0.0, gd = 0.0, gw = 0.0;
+    for (int bi = 0; bi < batch; ++bi) {
+        const double* l = lam + int64_t(bi) * total;
+        const double* xx = x + int64_t(bi) * total;
+        const double lc = l[row + c], xc = xx[row + c];
+        ge -= (sc * lc - se * l[row + nbc[0]]) * (xc - xx[row + nbc[0]]);
+        gn -= (sc * lc - sn * l[row + nbc[2]]) * (xc - xx[row + nbc[2]]);
+        double lx = 0.0;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) lx += K[d] * (xc - xx[row + nbc[d]]);
+        if (k + 1 < nz) {
+            gv -= (sc * lc - su * l[row + ncol + c]) * (xc - xx[row + ncol + c]);
+            lx += kup * (xc - xx[row + ncol + c]);
+        }
+        if (k > 0) lx += kdn * (xc - xx[row - ncol + c]);
+        gd -= lc * xc;
+        gw -= lc * lx;
+    }
+    gkh[i] = ge;
+    gkh[total + i] = gn;
+    if (k + 1 < nz) gkv[i] = gv;
+    gdl[i] = gd;
+    gs[i] = gw;
 }
 
 // ---------------------------------------------------------------------------

@@ -60,7 +60,11 @@ class Operator:
     ``nlevels=1`` the preconditioner is P_H^(Jac)(omega, n_coarse), and
     ``vcycle`` alone is the preconditioner-only solver PreOnly. ``kv2``
     (``[nz-2][ncol]``) selects the 9-cell stencil with couplings two levels
-    apart; ``face_grad`` then also returns their gradient.
+    apart; ``face_grad`` then also returns their gradient. ``s``
+    (``[nz][ncol]``, > 0) selects the non-symmetric row-weighted operator
+    H = delta + diag(s) L (needs ``cg="bicgstab"``); ``apply_adjoint``,
+    ``vcycle_adjoint`` and ``solve_adjoint`` work with H^T, and ``face_grad``
+    takes lam = H^-T g and also returns the gradient for ``s``.
     """
 
     _KRYLOV = {"standard": _lib.CG_STANDARD, "flexible": _lib.CG_FLEXIBLE,
@@ -74,7 +78,7 @@ class Operator:
 
     def __init__(self, N, nz, kh, kv, delta, nlevels, n_pre=2, n_post=2, n_coarse=4,
                  omega=0.8, precision="fp64", cg="standard", max_batch=1, device="cuda",
-                 kv2=None):
+                 kv2=None, s=None):
         self.lib = _lib.load()
         self.device = torch.device(device)
         if self.device.type == "cuda" and self.device.index is None:
@@ -83,9 +87,11 @@ class Operator:
         self.ncol = 6 * self.N * self.N
         self.precision = precision
         self.nine = kv2 is not None
+        self.weighted = s is not None
         self.cfg = _lib.Config(self.N, self.nz, self.nlevels, n_pre, n_post, n_coarse,
                                float(omega), _lib.FP32 if precision == "fp32" else _lib.FP64,
-                               self._krylov(cg), int(max_batch), 9 if self.nine else 7)
+                               self._krylov(cg), int(max_batch), 9 if self.nine else 7,
+                               1 if self.weighted else 0)
         self.max_batch = int(max_batch)
         self.cg = cg
         nbytes = self.lib.helmholtz_workspace_bytes(ctypes.byref(self.cfg))
@@ -105,11 +111,18 @@ class Operator:
         else:
             kv2 = None
         handle = ctypes.c_void_p()
+        kvp = kv.data_ptr() if kv is not None else None
         with torch.cuda.device(self.device):
-            code = self.lib.helmholtz_create9(
-                ctypes.byref(self.cfg), kh.data_ptr(), kv.data_ptr() if kv is not None else None,
-                kv2.data_ptr() if kv2 is not None else None, delta.data_ptr(), self._ws_ptr,
-                nbytes, _stream_ptr(self.device), ctypes.byref(handle))
+            if self.weighted:
+                s = _dev(s, torch.float64, self.device, (self.nz, self.ncol))
+                code = self.lib.helmholtz_create_weighted(
+                    ctypes.byref(self.cfg), kh.data_ptr(), kvp, delta.data_ptr(), s.data_ptr(),
+                    self._ws_ptr, nbytes, _stream_ptr(self.device), ctypes.byref(handle))
+            else:
+                code = self.lib.helmholtz_create9(
+                    ctypes.byref(self.cfg), kh.data_ptr(), kvp,
+                    kv2.data_ptr() if kv2 is not None else None, delta.data_ptr(), self._ws_ptr,
+                    nbytes, _stream_ptr(self.device), ctypes.byref(handle))
         _lib.check(code, "helmholtz_create")
         self._h = handle
 
@@ -137,21 +150,29 @@ class Operator:
         return v, squeeze
 
     # -- operations --------------------------------------------------------
-    def apply(self, x):
+    def apply(self, x, _fn="helmholtz_apply"):
         """y = H x (float64)."""
         x, sq = self._vec(x)
         y = torch.empty_like(x)
-        _lib.check(self.lib.helmholtz_apply(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
-                                            _stream_ptr(self.device)), "helmholtz_apply")
+        _lib.check(getattr(self.lib, _fn)(self._h, x.data_ptr(), y.data_ptr(), x.shape[0],
+                                          _stream_ptr(self.device)), _fn)
         return y[0] if sq else y
 
-    def vcycle(self, b):
+    def apply_adjoint(self, x):
+        """y = H^T x (float64)."""
+        return self.apply(x, "helmholtz_apply_adjoint")
+
+    def vcycle(self, b, _fn="helmholtz_vcycle"):
         """x = M b, one V-cycle from zero in the operator's precision (float64 in and out)."""
         b, sq = self._vec(b)
         x = torch.empty_like(b)
-        _lib.check(self.lib.helmholtz_vcycle(self._h, b.data_ptr(), x.data_ptr(), b.shape[0],
-                                             _stream_ptr(self.device)), "helmholtz_vcycle")
+        _lib.check(getattr(self.lib, _fn)(self._h, b.data_ptr(), x.data_ptr(), b.shape[0],
+                                          _stream_ptr(self.device)), _fn)
         return x[0] if sq else x
+
+    def vcycle_adjoint(self, b):
+        """One V-cycle of the transposed hierarchy (the preconditioner of H^T)."""
+        return self.vcycle(b, "helmholtz_vcycle_adjoint")
 
     def vcycle_f32(self, b):
         """x = M b entirely in float32."""
@@ -162,7 +183,11 @@ class Operator:
                    "helmholtz_vcycle_f32")
         return x[0] if sq else x
 
-    def solve(self, b, rtol=1e-8, maxiter=200, out=None) -> SolveResult:
+    def solve_adjoint(self, g, rtol=1e-8, maxiter=200, out=None) -> SolveResult:
+        """Solve H^T lam = g (the adjoint solve)."""
+        return self.solve(g, rtol, maxiter, out, _fn="helmholtz_solve_adjoint")
+
+    def solve(self, b, rtol=1e-8, maxiter=200, out=None, _fn="helmholtz_solve") -> SolveResult:
         """Preconditioned Krylov solve (the handle's ``cg`` method) from x = 0; returns
         the solution and per-RHS statistics."""
         b, sq = self._vec(b)
@@ -170,9 +195,9 @@ class Operator:
         nb = b.shape[0]
         iters = (ctypes.c_int32 * nb)()
         rel = (ctypes.c_double * nb)()
-        code = self.lib.helmholtz_solve(self._h, b.data_ptr(), x.data_ptr(), nb, float(rtol),
-                                        int(maxiter), iters, rel, _stream_ptr(self.device))
-        _lib.check(code, "helmholtz_solve", allow_not_converged=True)
+        code = getattr(self.lib, _fn)(self._h, b.data_ptr(), x.data_ptr(), nb, float(rtol),
+                                      int(maxiter), iters, rel, _stream_ptr(self.device))
+        _lib.check(code, _fn, allow_not_converged=True)
         return SolveResult(x[0] if sq else x, list(iters), list(rel), code == _lib.OK)
 
     def profile(self, enable: bool = True):
@@ -198,6 +223,13 @@ class Operator:
         gdl = torch.empty((self.nz, self.ncol), dtype=torch.float64, device=self.device)
         gkv2 = torch.empty((max(self.nz - 2, 0), self.ncol), dtype=torch.float64,
                            device=self.device) if self.nine else None
+        if self.weighted:
+            gs = torch.empty((self.nz, self.ncol), dtype=torch.float64, device=self.device)
+            _lib.check(self.lib.helmholtz_face_grad_weighted(
+                self._h, lam.data_ptr(), x.data_ptr(), lam.shape[0], gkh.data_ptr(),
+                gkv.data_ptr() if self.nz > 1 else None, gdl.data_ptr(), gs.data_ptr(),
+                _stream_ptr(self.device)), "helmholtz_face_grad_weighted")
+            return gkh, gkv, gdl, gs
         _lib.check(self.lib.helmholtz_face_grad9(
             self._h, lam.data_ptr(), x.data_ptr(), lam.shape[0], gkh.data_ptr(),
             gkv.data_ptr() if self.nz > 1 else None,

@@ -31,7 +31,7 @@ def _declared_functions():
 def test_every_declared_symbol_is_exported(lib):
     from paper_2002_00756_amd import _lib
     names = _declared_functions()
-    assert len(names) == 14
+    assert len(names) == 19
     for n in names:
         assert hasattr(lib, n), n
         assert n in _lib.SIGNATURES, n
@@ -40,10 +40,11 @@ def test_every_declared_symbol_is_exported(lib):
 def _cfg(N=12, nz=10, L=3, **kw):
     from paper_2002_00756_amd import _lib
     d = dict(n_pre=2, n_post=2, n_coarse=4, omega=0.8, mg_precision=0, cg_variant=0, max_batch=1,
-             stencil=7)
+             stencil=7, weighted=0)
     d.update(kw)
     return _lib.Config(N, nz, L, d["n_pre"], d["n_post"], d["n_coarse"], d["omega"],
-                       d["mg_precision"], d["cg_variant"], d["max_batch"], d["stencil"])
+                       d["mg_precision"], d["cg_variant"], d["max_batch"], d["stencil"],
+                       d["weighted"])
 
 
 def test_workspace_bytes(lib):
@@ -86,6 +87,16 @@ def test_create_rejects_before_touching_the_device(lib):
     assert lib.helmholtz_create9(ctypes.byref(_cfg(stencil=7)), dummy, dummy, dummy, dummy,
                                  dummy, 1 << 30, None, ctypes.byref(h)) == _lib.EINVAL
     assert lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(stencil=8))) == 0
+    # weighted operator: BiCGStab and the 7-point stencil only, through its own create
+    assert lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(weighted=1))) == 0
+    assert lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(weighted=1, cg_variant=2,
+                                                            stencil=9))) == 0
+    assert lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(weighted=1, cg_variant=2))) > 0
+    assert lib.helmholtz_create(ctypes.byref(_cfg(weighted=1, cg_variant=2)), dummy, dummy,
+                                dummy, dummy, 1 << 30, None, ctypes.byref(h)) == _lib.EINVAL
+    assert lib.helmholtz_create_weighted(ctypes.byref(_cfg(weighted=1, cg_variant=2)), dummy,
+                                         dummy, dummy, None, dummy, 1 << 30, None,
+                                         ctypes.byref(h)) == _lib.EINVAL
     assert lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(stencil=9))) > \
         lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(stencil=7)))
     assert not h.value
