@@ -296,6 +296,49 @@ def nine_cell_leg(Operator, torch, dev, _lib, steps=10, warmup=2):
     }
 
 
+def weighted_leg(Operator, torch, dev, steps=5, warmup=1):
+    """The non-symmetric operator H = delta + diag(s) L on the benchmark shape
+    (C192x70 coefficients, s ~ U[0.5, 1.5], the role of 1/rho*): BiCGStab with
+    one float32 6-level V-cycle per preconditioner application, to 1e-6; the
+    forward solve alone, and a gradient step (forward solve, adjoint solve with
+    H^T and the transposed V-cycle, weighted face gradients)."""
+    w = workloads.C192x70
+    kh, kv, delta = workloads.workload_coefficients(w)
+    sw = workloads.row_weights(w.N, w.nz)
+    op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", cg="bicgstab",
+                  device=dev, s=sw)
+    b = torch.from_numpy(workloads.rhs(w.N, w.nz)[0]).to(dev)
+    g = torch.from_numpy(workloads.loss_weights(w.N, w.nz)[0]).to(dev)
+    for _ in range(warmup):
+        op.solve(b, rtol=1e-6)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        res = op.solve(b, rtol=1e-6)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / steps * 1e3
+    t = time.perf_counter()
+    for _ in range(steps):
+        xf = op.solve(b, rtol=1e-6)
+        lam = op.solve_adjoint(g, rtol=1e-6)
+        op.face_grad(lam.x, xf.x)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t) / steps * 1e3
+    bn, gn = torch.linalg.norm(b), torch.linalg.norm(g)
+    n = w.n
+    gbs = bicgstab_bytes_per_unknown(vcycle_words(w.nlevels, 2, 2, 4), True) * res.iters[0] * n
+    return {
+        "workload": f"{w.name} coefficients with row weights s ~ U[0.5, 1.5] ({n} unknowns)",
+        "solver": "BiCGStab + float32 MG(6) V-cycle, rtol 1e-6",
+        "solves_per_s": 1e3 / ms, "ms_per_solve": ms, "iters": res.iters[0],
+        "true_relres": float(torch.linalg.norm(b - op.apply(res.x)) / bn),
+        "GBps": gbs / (ms * 1e-3) / 1e9,
+        "adjoint_iters": lam.iters[0],
+        "adjoint_true_relres": float(torch.linalg.norm(g - op.apply_adjoint(lam.x)) / gn),
+        "fwd_adj_grad_step_ms": step_ms,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -307,6 +350,8 @@ def main():
     ap.add_argument("--no-batch-leg", action="store_true",
                     help="skip the C384x70 batch-of-4 forward+adjoint measurement")
     ap.add_argument("--cg", default="standard", choices=["standard", "flexible"])
+    ap.add_argument("--no-weighted", action="store_true",
+                    help="skip the non-symmetric (row-weighted) operator measurement")
     ap.add_argument("--no-nine-cell", action="store_true",
                     help="skip the 9-cell stencil measurement")
     ap.add_argument("--no-solver-comparison", action="store_true",
@@ -507,6 +552,8 @@ def main():
         out["solver_comparison"] = solver_comparison(Operator, torch, dev)
     if not args.no_nine_cell and args.workload == "C192x70":
         out["nine_cell_C192x70"] = nine_cell_leg(Operator, torch, dev, _lib)
+    if not args.no_weighted and args.workload == "C192x70":
+        out["nonsymmetric_C192x70"] = weighted_leg(Operator, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, kh, kv, delta, b_np, int(round(it64)))
     print(json.dumps(out), flush=True)
