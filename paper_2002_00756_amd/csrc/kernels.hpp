@@ -585,8 +585,8 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
         const int k0 = kc * KC;
         // all loads of the chunk are issued before any is used
         T xc[KC + 2], kvv[KC + 1], dl[KC], xn[KC][4], kh[KC][4];
-        // weighted: own weights (k0-1 .. k0+KC; H^T) or (k0 .. k0+KC-1; H),
-        // neighbours' weights (H^T)
+        // weighted operator: own weights at k0-1 .. k0+KC (as xc) and, for
+        // H^T, the neighbours' weights
         T sc[KC + 2], sn[KC][4];
 #pragma unroll
         for (int j = 0; j < KC + 2; ++j) {
@@ -654,9 +654,9 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
                     v += sc[j + 1] * f;
                 } else {
 #pragma unroll
-                for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
-                v += kvv[j + 1] * (xo - xc[j + 2]);
-                v += kvv[j] * (xo - xc[j]);
+                    for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
+                    v += kvv[j + 1] * (xo - xc[j + 2]);
+                    v += kvv[j] * (xo - xc[j]);
                 }
                 if constexpr (K2) {
                     // x[k-2] and x[k+2] (xc[i] holds x[k0-1+i])
