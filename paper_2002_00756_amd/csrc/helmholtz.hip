@@ -473,9 +473,6 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
 }
 
 // ---- V-cycle (Algorithm 1) ------------------------------------------------
-// Level l smooths b_l into out_l, using tmp_l as the Jacobi ping-pong partner.
-// The writes of x on one level alternate between the two buffers; they are
-// assigned from the last write backwards so that the last lands in out_l.
 // Number of x writes on level l and the buffer that write j goes to: the
 // writes alternate between out_l and tmp_l, assigned from the last one
 // backwards so that the last lands in out_l.

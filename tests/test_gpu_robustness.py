@@ -132,3 +132,26 @@ def test_batch_of_eight_matches_single_solves():
     lev = mesh.Level(24)
     rkh, rkv, rdl = adjoint.face_gradients(lev, lam.cpu().numpy(), res.x.cpu().numpy())
     assert np.allclose(gkh.cpu().numpy(), rkh, rtol=1e-12, atol=1e-12 * np.abs(rkh).max())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_members_converging_at_different_iterations(precision):
+    """A member that has converged stops while the others go on: every later
+    launch must leave it untouched. Each member equals its own solve, bit for
+    bit (no kernel mixes right-hand sides)."""
+    from paper_2002_00756_amd import Operator
+    print(f"batch with staggered convergence {precision}", flush=True)
+    _, (kh, kv, delta) = _hier(24, 30, 4, w_v=1000.0, graded=True)
+    op = Operator(24, 30, kh, kv, delta, 4, precision=precision, max_batch=3)
+    r = workloads.rhs(24, 30)[0]
+    # a random right-hand side and one constant along each column (the oracle
+    # needs 5 and 6 iterations at 1e-8), and a zero one
+    b = np.stack([r, np.tile(r.mean(axis=0), (30, 1)), np.zeros_like(r)])
+    res = op.solve(torch.from_numpy(b).cuda(), rtol=1e-8)
+    assert res.converged and res.iters[2] == 0 and not res.x[2].any()
+    if precision == "fp64":
+        assert res.iters[0] < res.iters[1]
+    for i in (0, 1):
+        single = op.solve(torch.from_numpy(b[i]).cuda(), rtol=1e-8)
+        assert single.iters[0] == res.iters[i]
+        assert torch.equal(single.x, res.x[i])
