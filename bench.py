@@ -394,8 +394,8 @@ def main():
                          "size, no JSON")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design only).", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
+              "(it has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
 
     import torch
