@@ -302,6 +302,16 @@ LevelData<T>& data(helmholtz_s* h, int l) {
 // ---- sweep launch: compile-time bound on levels per thread ---------------
 inline int sweep_mid(int nz) { return nz / 2; }
 
+// Whether one sweep over level l streams far more data than the last-level
+// cache (256 MiB Infinity Cache) holds: then its read-once streams bypass the
+// cache (k_sweep with NTS). On smaller levels the next kernel finds the
+// previous one's output there, and plain accesses are faster.
+bool streams_past_cache(const helmholtz_s* h, int l, int batch, size_t word) {
+    constexpr int64_t kLastLevelCache = int64_t(256) << 20;
+    // kh[2], cc, mm and the neighbour couplings; b, x, x_new per right-hand side
+    return int64_t(h->lev[l].nvp) * int64_t(word) * (5 + 3 * int64_t(batch)) > kLastLevelCache;
+}
+
 template <typename T, int JMAX, int MODE, int TC, bool VARIANTS>
 void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T* xc, T* y,
                     int batch, const int* active, hipStream_t s) {
@@ -316,15 +326,31 @@ void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T
                            view<T>(h, l), b, x, xc, par, nvp_c, y, T(h->cfg.omega), batch, active,
                            sweep_mid(h->nz));
     };
+    // only the large levels use 32-column tiles and can stream past the cache
+    constexpr bool kCanStream = TC == kTile;
+    const bool nts = kCanStream && streams_past_cache(h, l, batch, sizeof(T));
+    auto pick = [&](auto plain, auto streamed) {
+        if constexpr (kCanStream) {
+            if (nts) {
+                go(streamed);
+                return;
+            }
+        }
+        go(plain);
+    };
     if constexpr (VARIANTS) {
         if (h->weighted && h->adj)
-            go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowWT>);
+            pick(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowWT>,
+                 k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowWT, kCanStream>);
         else if (h->weighted)
-            go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowW>);
+            pick(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowW>,
+                 k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kRowW, kCanStream>);
         else
-            go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, true>);
+            pick(k_sweep<T, JMAX, MODE, TC, kBlock, 0, true>,
+                 k_sweep<T, JMAX, MODE, TC, kBlock, 0, true, kSym, kCanStream>);
     } else {
-        go(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false>);
+        pick(k_sweep<T, JMAX, MODE, TC, kBlock, 0, false>,
+             k_sweep<T, JMAX, MODE, TC, kBlock, 0, false, kSym, kCanStream>);
     }
     if (prof)  // b, x, kh[2], cc, mm (, kv2) read; x_new written
         prof_end(h, HELMHOLTZ_PROF_SWEEP_FINE,

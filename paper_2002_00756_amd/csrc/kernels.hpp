@@ -240,8 +240,11 @@ struct SweepTile {
     static size_t lds_bytes(int nz) { return size_t(2 * nz + 2) * TC * sizeof(T); }
 };
 
+// NTS: b, the column factors and x_new are streamed with non-temporal loads
+// and stores (for levels much larger than the last-level cache), so that the
+// cache keeps x and the face couplings, which neighbouring tiles read again.
 template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = kBlock,
-          int CH_ = 0, bool K2 = false, int SC = kSym>
+          int CH_ = 0, bool K2 = false, int SC = kSym, bool NTS = false>
 __global__ void __launch_bounds__(NT)
 k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         const T* __restrict__ xc, const int32_t* __restrict__ parent, int nvp_c,
@@ -291,6 +294,10 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         fS = L.fface[ncol + c];
         if (kHasP) pn[4] = tile_base(parent[c], nz);
     }
+    auto ld = [](const T* p) -> T {
+        if constexpr (NTS) return __builtin_nontemporal_load(p);
+        else return *p;
+    };
     auto xv = [&](int k, int off, int poff) -> T {
         T v = T(0);
         if (kHasX) v = x[off + kTile * k];
@@ -322,10 +329,10 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
             for (int d = 0; d < 4; ++d) vsn[jj][d] = T(1);
             if (j < JMAX && k < nz && valid) {
                 const int o = ob + kTile * k;
-                vb[jj] = b[o];
+                vb[jj] = ld(b + o);
                 if constexpr (SC != kSym) vs[jj] = L.s[o];
-                vc[jj] = L.cc[o];
-                vm[jj] = L.mm[o];
+                vc[jj] = ld(L.cc + o);
+                vm[jj] = ld(L.mm + o);
                 if (MODE != kZero) {
                     vk[jj][0] = L.kh[o];
                     vk[jj][1] = L.kh[fW + uint32_t(kTile * k)];
@@ -384,7 +391,9 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         if (k < nz) {
             T z = R[k * TC + lc];
             if constexpr (SC == kRowWT) z = z / so[j];
-            y[ob + kTile * k] = (MODE == kZero) ? om * z : om1 * xo[j] + om * z;
+            const T v = (MODE == kZero) ? om * z : om1 * xo[j] + om * z;
+            if constexpr (NTS) __builtin_nontemporal_store(v, y + ob + kTile * k);
+            else y[ob + kTile * k] = v;
         }
     }
 }
