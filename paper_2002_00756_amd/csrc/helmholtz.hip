@@ -432,20 +432,34 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
         hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), c.child, c.ncol, c.nvp,
                            b, x, bc, batch, kchunk, nkc, active);
     };
+    // paired loads (the library's own buffers): streamed past the cache on
+    // levels far larger than it
+    const bool nts = streams_past_cache(h, l, batch, sizeof(T));
+    auto pick = [&](auto plain, auto streamed) {
+        if (nts) go(streamed);
+        else go(plain);
+    };
     if (!x) {
-        if (pair) go(k_resid_restrict<T, true, true>);
+        if (pair) pick(k_resid_restrict<T, true, true>, k_resid_restrict<T, true, true, false, kSym, true>);
         else go(k_resid_restrict<T, true, false>);
     } else if (h->nine) {
-        if (pair) go(k_resid_restrict<T, false, true, true>);
+        if (pair)
+            pick(k_resid_restrict<T, false, true, true>,
+                 k_resid_restrict<T, false, true, true, kSym, true>);
         else go(k_resid_restrict<T, false, false, true>);
     } else if (h->weighted && h->adj) {
-        if (pair) go(k_resid_restrict<T, false, true, false, kRowWT>);
+        if (pair)
+            pick(k_resid_restrict<T, false, true, false, kRowWT>,
+                 k_resid_restrict<T, false, true, false, kRowWT, true>);
         else go(k_resid_restrict<T, false, false, false, kRowWT>);
     } else if (h->weighted) {
-        if (pair) go(k_resid_restrict<T, false, true, false, kRowW>);
+        if (pair)
+            pick(k_resid_restrict<T, false, true, false, kRowW>,
+                 k_resid_restrict<T, false, true, false, kRowW, true>);
         else go(k_resid_restrict<T, false, false, false, kRowW>);
     } else {
-        if (pair) go(k_resid_restrict<T, false, true>);
+        if (pair)
+            pick(k_resid_restrict<T, false, true>, k_resid_restrict<T, false, true, false, kSym, true>);
         else go(k_resid_restrict<T, false, false>);
     }
 }

@@ -728,7 +728,23 @@ __device__ __forceinline__ void load_pair(const T* __restrict__ p, int64_t i, T&
     }
 }
 
-template <typename T, bool ZEROX, bool PAIR, bool K2 = false, int SC = kSym>
+// The same with non-temporal loads, for a stream that is read exactly once.
+template <typename T, bool PAIR>
+__device__ __forceinline__ void load_pair_nt(const T* __restrict__ p, int64_t i, T& a, T& c) {
+    if (PAIR) {
+        typedef T V2 __attribute__((ext_vector_type(2)));
+        const V2 v = __builtin_nontemporal_load(reinterpret_cast<const V2*>(p + i));
+        a = v.x;
+        c = v.y;
+    } else {
+        a = __builtin_nontemporal_load(p + i);
+        c = __builtin_nontemporal_load(p + i + 1);
+    }
+}
+
+// NTS: b and delta, each read exactly once, bypass the last-level cache (for
+// levels far larger than it; see k_sweep).
+template <typename T, bool ZEROX, bool PAIR, bool K2 = false, int SC = kSym, bool NTS = false>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
                  const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
@@ -744,6 +760,10 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
     b += rhs * nv;
     if (!ZEROX) x += rhs * nv;
     bc += rhs * int64_t(nvp_c) + tile_base(C, nz);
+    auto load_once = [](const T* p, int64_t i, T& a, T& c) {
+        if constexpr (NTS) load_pair_nt<T, PAIR>(p, i, a, c);
+        else load_pair<T, PAIR>(p, i, a, c);
+    };
     // children (0,0), (1,0) share a tile and are adjacent, as are (0,1), (1,1)
     int ch[4], cb[4];
 #pragma unroll
@@ -756,8 +776,8 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
         for (int k = k0; k < k1; ++k) {
             const int r = kTile * k;
             T v0, v1, v2, v3;
-            load_pair<T, PAIR>(b, r + cb[0], v0, v1);
-            load_pair<T, PAIR>(b, r + cb[2], v2, v3);
+            load_once(b, r + cb[0], v0, v1);
+            load_once(b, r + cb[2], v2, v3);
             bc[r] = ((v0 + v1) + v2) + v3;
         }
         return;
@@ -840,10 +860,10 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
                 su(xup[2], xup[3], r + kTile + cb[2]);
             }
         }
-        load_pair<T, PAIR>(b, r + cb[0], vb[0], vb[1]);
-        load_pair<T, PAIR>(b, r + cb[2], vb[2], vb[3]);
-        load_pair<T, PAIR>(F.dl, r + cb[0], vd[0], vd[1]);
-        load_pair<T, PAIR>(F.dl, r + cb[2], vd[2], vd[3]);
+        load_once(b, r + cb[0], vb[0], vb[1]);
+        load_once(b, r + cb[2], vb[2], vb[3]);
+        load_once(F.dl, r + cb[0], vd[0], vd[1]);
+        load_once(F.dl, r + cb[2], vd[2], vd[3]);
         load_pair<T, PAIR>(F.kv, r + cb[0], vkv[0], vkv[1]);
         load_pair<T, PAIR>(F.kv, r + cb[2], vkv[2], vkv[3]);
 #pragma unroll
