@@ -499,6 +499,13 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
             case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk, true>); break;
             default: go(k_apply<T, kDotNone, kApplyChunk, true>); break;
         }
+    } else if (streams_past_cache(h, l, batch, sizeof(T))) {
+        switch (dot) {
+            case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, false, kSym, true>); break;
+            case kDotWY: go(k_apply<T, kDotWY, kApplyChunk, false, kSym, true>); break;
+            case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk, false, kSym, true>); break;
+            default: go(k_apply<T, kDotNone, kApplyChunk, false, kSym, true>); break;
+        }
     } else {
         switch (dot) {
             case kDotXY: go(k_apply<T, kDotXY, kApplyChunk>); break;

@@ -567,7 +567,9 @@ k_finalize(CgState st, int mode, int cnt, int seq) {
 // kDotWYYY w . y and y . y (BiCGStab: (t, s), (t, t)). Partial sums per block.
 enum { kDotNone = 0, kDotXY = 1, kDotWY = 2, kDotWYYY = 3 };
 
-template <typename T, int DOT, int KC, bool K2 = false, int SC = kSym>
+// NTS: delta (read once) and y bypass the last-level cache (for levels far
+// larger than it; see k_sweep).
+template <typename T, int DOT, int KC, bool K2 = false, int SC = kSym, bool NTS = false>
 __global__ void __launch_bounds__(kBlock)
 k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
         int batch, int nkc, CgState st, const int* __restrict__ active) {
@@ -629,7 +631,8 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
             for (int d = 0; d < 4; ++d) xn[j][d] = kh[j][d] = T(0);
             if (k < nz) {
                 const int o = ob + kTile * k;
-                dl[j] = L.dl[o];
+                if constexpr (NTS) dl[j] = __builtin_nontemporal_load(L.dl + o);
+                else dl[j] = L.dl[o];
 #pragma unroll
                 for (int d = 0; d < 4; ++d) xn[j][d] = x[nb[d] + kTile * k];
 #pragma unroll
@@ -674,7 +677,8 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
                     v += k2v[j + 2] * (xo - xp2);
                     v += k2v[j] * (xo - xm2);
                 }
-                y[ob + kTile * k] = v;
+                if constexpr (NTS) __builtin_nontemporal_store(v, y + ob + kTile * k);
+                else y[ob + kTile * k] = v;
                 if (DOT == kDotXY) acc += double(xo) * double(v);
                 if (DOT >= kDotWY) acc += double(w[ob + kTile * k]) * double(v);
                 if (DOT == kDotWYYY) acc2 += double(v) * double(v);
