@@ -240,12 +240,22 @@ struct SweepTile {
     static size_t lds_bytes(int nz) { return size_t(2 * nz + 2) * TC * sizeof(T); }
 };
 
+// Waves per SIMD asked of the register allocator: the float32 sweep with
+// prolongation would otherwise take 85 registers and run 5 waves per SIMD;
+// held to 80 it keeps the 6 of the plain sweep (a few values spill).
+template <typename T, int JMAX, int MODE, bool K2, int SC>
+struct SweepWaves {
+    static constexpr int value =
+        (sizeof(T) == 4 && MODE == kProlong && !K2 && SC == kSym && JMAX <= 9) ? 6 : 1;
+};
+
 // NTS: b, the column factors and x_new are streamed with non-temporal loads
 // and stores (for levels much larger than the last-level cache), so that the
 // cache keeps x and the face couplings, which neighbouring tiles read again.
 template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = kBlock,
           int CH_ = 0, bool K2 = false, int SC = kSym, bool NTS = false>
 __global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(SweepWaves<T, JMAX, MODE, K2, SC>::value)))
 k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
         const T* __restrict__ xc, const int32_t* __restrict__ parent, int nvp_c,
         T* __restrict__ y, T omega, int batch, const int* __restrict__ active, int mid) {
