@@ -440,7 +440,9 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
         else go(plain);
     };
     if (!x) {
-        if (pair) pick(k_resid_restrict<T, true, true>, k_resid_restrict<T, true, true, false, kSym, true>);
+        if (pair)
+            pick(k_resid_restrict<T, true, true>,
+                 k_resid_restrict<T, true, true, false, kSym, true>);
         else go(k_resid_restrict<T, true, false>);
     } else if (h->nine) {
         if (pair)
@@ -459,7 +461,8 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
         else go(k_resid_restrict<T, false, false, false, kRowW>);
     } else {
         if (pair)
-            pick(k_resid_restrict<T, false, true>, k_resid_restrict<T, false, true, false, kSym, true>);
+            pick(k_resid_restrict<T, false, true>,
+                 k_resid_restrict<T, false, true, false, kSym, true>);
         else go(k_resid_restrict<T, false, false>);
     }
 }
@@ -1050,21 +1053,30 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     if (!any) return finish(HELMHOLTZ_OK);
     if (bicg) return finish(bicgstab_loop(h, x, batch, maxiter, bnorm2, it, rel, s));
 
+    // vectors far larger than the last-level cache: the streams that are not
+    // read again soon bypass it (see the kernels)
+    const bool vnt = streams_past_cache(h, 0, batch, sizeof(double));
+    auto dot_rz = [&](const double* q) {
+        auto go = [&](auto kern, auto z) {
+            hipLaunchKernelGGL(kern, red, blk, 0, s, h->r, z, q, n, kRedBlocks, st);
+        };
+        if (mixed) vnt ? go(k_dot_rz<float, true>, z32) : go(k_dot_rz<float, false>, z32);
+        else vnt ? go(k_dot_rz<double, true>, h->z) : go(k_dot_rz<double, false>, h->z);
+    };
+    auto p_update = [&](int init) {
+        auto go = [&](auto kern, auto z) {
+            hipLaunchKernelGGL(kern, red, blk, 0, s, z, h->p, n, kRedBlocks, h->sc, h->active,
+                               init);
+        };
+        if (mixed) vnt ? go(k_p_update<float, true>, z32) : go(k_p_update<float, false>, z32);
+        else vnt ? go(k_p_update<double, true>, h->z) : go(k_p_update<double, false>, h->z);
+    };
+
     // z = M r, rho = r.z, p = z
     if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
-    if (mixed)
-        hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, nullptr, n, kRedBlocks,
-                           st);
-    else
-        hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, nullptr, n,
-                           kRedBlocks, st);
+    dot_rz(nullptr);
     hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRho), kRedBlocks, 0);
-    if (mixed)
-        hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks, h->sc,
-                           h->active, 1);
-    else
-        hipLaunchKernelGGL((k_p_update<double>), red, blk, 0, s, h->z, h->p, n, kRedBlocks, h->sc,
-                           h->active, 1);
+    p_update(1);
 
     const int ntile0 = (h->lev[0].ncol + kBlock - 1) / kBlock;
     const int nkc0 = (h->nz + kApplyChunk - 1) / kApplyChunk;
@@ -1077,8 +1089,12 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
                            0);
         // x += alpha p, r -= alpha q, ||r||^2 and the convergence flags, published
-        hipLaunchKernelGGL(k_cg_update, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q, v0.ncol,
-                           h->nz, v0.nvp, st);
+        if (vnt)
+            hipLaunchKernelGGL(k_cg_update<true>, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q,
+                               v0.ncol, h->nz, v0.nvp, st);
+        else
+            hipLaunchKernelGGL(k_cg_update<false>, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q,
+                               v0.ncol, h->nz, v0.nvp, st);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRR), ntile32, iter);
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
         if (int e = wait_published(h, s, was_active, iter)) return e;
@@ -1098,21 +1114,10 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         }
         // z = M r, beta, p = z + beta p
         if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
-        const double* qarg = flex ? h->q : nullptr;
-        if (mixed)
-            hipLaunchKernelGGL((k_dot_rz<float>), red, blk, 0, s, h->r, z32, qarg, n, kRedBlocks,
-                               st);
-        else
-            hipLaunchKernelGGL((k_dot_rz<double>), red, blk, 0, s, h->r, h->z, qarg, n,
-                               kRedBlocks, st);
+        dot_rz(flex ? h->q : nullptr);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st,
                            int(flex ? kFinBetaFlex : kFinBeta), kRedBlocks, 0);
-        if (mixed)
-            hipLaunchKernelGGL((k_p_update<float>), red, blk, 0, s, z32, h->p, n, kRedBlocks,
-                               h->sc, h->active, 0);
-        else
-            hipLaunchKernelGGL((k_p_update<double>), red, blk, 0, s, h->z, h->p, n, kRedBlocks,
-                               h->sc, h->active, 0);
+        p_update(0);
     }
     // the caller may read x as soon as this returns on the host
     HH_CHECK(hipStreamSynchronize(s));

@@ -90,6 +90,18 @@ struct LevelView {
     const T* __restrict__ s;    // row weight; null for the symmetric operator
 };
 
+// Loads and stores of a stream that the cache need not keep (NT: non-temporal).
+template <bool NT, typename T>
+__device__ __forceinline__ T stream_load(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void stream_store(T* p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 // Operator form a kernel is built for: symmetric, row-weighted H = delta + S L,
 // or its transpose H^T = delta + L S.
 enum { kSym = 0, kRowW = 1, kRowWT = 2 };
@@ -1160,7 +1172,10 @@ k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restri
 }
 
 // x += alpha p (x in the ABI layout); r -= alpha q; r32 = float(r); partial
-// ||r||^2 per tile.
+// ||r||^2 per tile. NT (vectors far larger than the last-level cache): x, q
+// and r, whose next reader comes after a whole V-cycle, bypass the cache, so
+// that it keeps r32 for the first smoothing sweep.
+template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
             const double* __restrict__ p, const double* __restrict__ q, int ncol, int nz, int nvp,
@@ -1175,9 +1190,10 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ 
         const int64_t ia = t.rhs * n + t.c, it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
         for (int k = t.g; k < nz; k += kTileGroups) {
             const int64_t o = it + kTile * k;
-            x[ia + int64_t(k) * ncol] += alpha * p[o];
-            const double v = r[o] - alpha * q[o];
-            r[o] = v;
+            double* xk = x + ia + int64_t(k) * ncol;
+            const double v = stream_load<NT>(r + o) - alpha * stream_load<NT>(q + o);
+            stream_store<NT>(xk, stream_load<NT>(xk) + alpha * p[o]);
+            stream_store<NT>(r + o, v);
             if (r32) r32[o] = float(v);
             acc += v * v;
         }
@@ -1202,8 +1218,9 @@ k_retile(const S* __restrict__ src, D* __restrict__ dst, int ncol, int nz, int n
     }
 }
 
-// partial r . z (and z . q for the flexible beta).
-template <typename Z>
+// partial r . z (and z . q for the flexible beta). NT: r bypasses the cache,
+// which keeps z for the direction update that follows.
+template <typename Z, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __restrict__ q,
          int64_t n, int nblk, CgState st) {
@@ -1217,7 +1234,7 @@ k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __
 #pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
         const double zv = double(z[off + i]);
-        a1 += r[off + i] * zv;
+        a1 += stream_load<NT>(r + off + i) * zv;
         if (q) a2 += zv * q[off + i];
     }
     const double s1 = block_sum(a1, sh);
@@ -1229,8 +1246,9 @@ k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __
     store_partial(st, rhs, blk, s1, s2, q != nullptr);
 }
 
-// p = z + beta p (init: p = z).
-template <typename Z>
+// p = z + beta p (init: p = z). NT: z, read for the last time, bypasses the
+// cache, which keeps p for the apply that follows.
+template <typename Z, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
            const double* __restrict__ sc, const int* __restrict__ active, int init) {
@@ -1242,7 +1260,7 @@ k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
     const int64_t off = int64_t(rhs) * n;
 #pragma unroll 4
     for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        const double zv = double(z[off + i]);
+        const double zv = double(stream_load<NT>(z + off + i));
         p[off + i] = init ? zv : zv + beta * p[off + i];
     }
 }
@@ -1334,7 +1352,8 @@ k_bicg_s(const double* __restrict__ r, const double* __restrict__ v, double* __r
     grid_range(n, nblk, blk, i0, i1);
     const int64_t off = int64_t(rhs) * n;
 #pragma unroll 4
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) s[off + i] = r[off + i] - alpha * v[off + i];
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock)
+        s[off + i] = r[off + i] - alpha * v[off + i];
 }
 
 // x += alpha p_hat + omega s_hat (x in the ABI layout); r = s - omega t;
