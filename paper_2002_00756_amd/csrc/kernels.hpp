@@ -261,9 +261,10 @@ struct SweepWaves {
         (sizeof(T) == 4 && MODE == kProlong && !K2 && SC == kSym && JMAX <= 9) ? 6 : 1;
 };
 
-// NTS: b, the column factors and x_new are streamed with non-temporal loads
-// and stores (for levels much larger than the last-level cache), so that the
-// cache keeps x and the face couplings, which neighbouring tiles read again.
+// NTS: b and the column factors, read once, are streamed with non-temporal
+// loads (for levels much larger than the last-level cache), so that the cache
+// keeps x and the face couplings, which neighbouring tiles read again, and
+// x_new, which the next kernel reads.
 template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = kBlock,
           int CH_ = 0, bool K2 = false, int SC = kSym, bool NTS = false>
 __global__ void __launch_bounds__(NT)
@@ -414,8 +415,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
             T z = R[k * TC + lc];
             if constexpr (SC == kRowWT) z = z / so[j];
             const T v = (MODE == kZero) ? om * z : om1 * xo[j] + om * z;
-            if constexpr (NTS) __builtin_nontemporal_store(v, y + ob + kTile * k);
-            else y[ob + kTile * k] = v;
+            y[ob + kTile * k] = v;
         }
     }
 }
