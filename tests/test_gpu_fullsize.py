@@ -70,3 +70,23 @@ def test_mixed_solve_full_size_manufactured(c192):
           f"error vs x* {err:.2e}", flush=True)
     assert true <= 1.05e-6
     assert err <= 1e-4
+
+
+def test_batch_of_two_full_size(c192):
+    """At this size the finest level's kernels stream past the last-level cache
+    (non-temporal variants); a batch of two right-hand sides must give each its
+    own solve, bit for bit."""
+    from paper_2002_00756_amd import Operator
+    w, hier, _, _ = c192
+    kh, kv, delta = workloads.workload_coefficients(w)
+    op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", max_batch=2)
+    b = torch.from_numpy(workloads.rhs(w.N, w.nz, 2, seed=11)).cuda()
+    res = op.solve(b, rtol=1e-6)
+    assert res.converged
+    for i in range(2):
+        single = op.solve(b[i], rtol=1e-6)
+        assert single.iters[0] == res.iters[i]
+        assert torch.equal(single.x, res.x[i])
+    x = res.x[1].cpu().numpy()
+    bn = b[1].cpu().numpy()
+    assert np.linalg.norm(bn - hier.apply(0, x)) / np.linalg.norm(bn) <= 1.05e-6
