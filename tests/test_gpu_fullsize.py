@@ -90,3 +90,36 @@ def test_batch_of_two_full_size(c192):
     x = res.x[1].cpu().numpy()
     bn = b[1].cpu().numpy()
     assert np.linalg.norm(bn - hier.apply(0, x)) / np.linalg.norm(bn) <= 1.05e-6
+
+
+def test_nine_cell_and_weighted_solves_full_size():
+    """The 9-cell operator (CG) and the row-weighted operator (BiCGStab, forward
+    and adjoint) at the benchmark's size, through the streamed kernel variants
+    of their V-cycles: true float64 residuals by the oracle's own apply."""
+    from paper_2002_00756_amd import Operator
+    w = workloads.C192x70
+    kh, kv, delta = workloads.workload_coefficients(w)
+    lev = mesh.Level(w.N)
+    b = workloads.rhs(w.N, w.nz)[0]
+    bd = torch.from_numpy(b).cuda()
+
+    def true_rel(x, **kw):
+        return np.linalg.norm(b - helmholtz.apply(lev, kh, kv, delta, x, **kw)) / np.linalg.norm(b)
+
+    print("9-cell solve at C192x70", flush=True)
+    w9 = workloads.C192x70_9
+    kv2 = workloads.workload_kv2(w9)
+    op9 = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", kv2=kv2)
+    r9 = op9.solve(bd, rtol=1e-6)
+    assert r9.converged
+    assert true_rel(r9.x.cpu().numpy(), kv2=kv2) <= 1.05e-6
+    del op9
+
+    print("row-weighted solves at C192x70", flush=True)
+    s = workloads.row_weights(w.N, w.nz)
+    opw = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", cg="bicgstab", s=s)
+    rf = opw.solve(bd, rtol=1e-6)
+    ra = opw.solve_adjoint(bd, rtol=1e-6)
+    assert rf.converged and ra.converged
+    assert true_rel(rf.x.cpu().numpy(), s=s) <= 1.05e-6
+    assert true_rel(ra.x.cpu().numpy(), s=s, transpose=True) <= 1.05e-6
