@@ -123,3 +123,28 @@ def test_nine_cell_and_weighted_solves_full_size():
     assert rf.converged and ra.converged
     assert true_rel(rf.x.cpu().numpy(), s=s) <= 1.05e-6
     assert true_rel(ra.x.cpu().numpy(), s=s, transpose=True) <= 1.05e-6
+
+
+@pytest.mark.parametrize("form", ["nine_cell", "weighted"])
+def test_vcycle_full_size_nine_cell_and_weighted(form):
+    """Float64 V-cycle of the 9-cell and of the row-weighted operator against
+    the oracle at the benchmark's size (the streamed kernel variants of those
+    operators), to 1e-10."""
+    from paper_2002_00756_amd import Operator
+    w = workloads.C192x70
+    kh, kv, delta = workloads.workload_coefficients(w)
+    levels, parents, childs = mesh.hierarchy(w.N, w.nlevels)
+    if form == "nine_cell":
+        kv2 = workloads.workload_kv2(workloads.C192x70_9)
+        hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta, kv2=kv2)
+        op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp64", kv2=kv2)
+    else:
+        s = workloads.row_weights(w.N, w.nz)
+        hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta, s=s)
+        op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp64", cg="bicgstab",
+                      s=s)
+    print(f"oracle {form} V-cycle at C192x70", flush=True)
+    b = workloads.rhs(w.N, w.nz, seed=12)[0]
+    ref = multigrid.vcycle(hier, b)
+    z = op.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert _rel(z, ref) <= 1e-10
