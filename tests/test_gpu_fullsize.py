@@ -125,11 +125,11 @@ def test_nine_cell_and_weighted_solves_full_size():
     assert true_rel(ra.x.cpu().numpy(), s=s, transpose=True) <= 1.05e-6
 
 
-@pytest.mark.parametrize("form", ["nine_cell", "weighted"])
+@pytest.mark.parametrize("form", ["nine_cell", "weighted", "weighted_transposed"])
 def test_vcycle_full_size_nine_cell_and_weighted(form):
-    """Float64 V-cycle of the 9-cell and of the row-weighted operator against
-    the oracle at the benchmark's size (the streamed kernel variants of those
-    operators), to 1e-10."""
+    """Float64 V-cycle of the 9-cell and of the row-weighted operator (and of
+    its transpose) against the oracle at the benchmark's size (the streamed
+    kernel variants of those operators), to 1e-10."""
     from paper_2002_00756_amd import Operator
     w = workloads.C192x70
     kh, kv, delta = workloads.workload_coefficients(w)
@@ -138,13 +138,17 @@ def test_vcycle_full_size_nine_cell_and_weighted(form):
         kv2 = workloads.workload_kv2(workloads.C192x70_9)
         hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta, kv2=kv2)
         op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp64", kv2=kv2)
-    else:
+    else:  # row-weighted, H or H^T
         s = workloads.row_weights(w.N, w.nz)
         hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta, s=s)
         op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp64", cg="bicgstab",
                       s=s)
     print(f"oracle {form} V-cycle at C192x70", flush=True)
     b = workloads.rhs(w.N, w.nz, seed=12)[0]
-    ref = multigrid.vcycle(hier, b)
-    z = op.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
+    if form == "weighted_transposed":
+        ref = multigrid.vcycle(hier.transpose(), b)
+        z = op.vcycle_adjoint(torch.from_numpy(b).cuda()).cpu().numpy()
+    else:
+        ref = multigrid.vcycle(hier, b)
+        z = op.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
     assert _rel(z, ref) <= 1e-10
