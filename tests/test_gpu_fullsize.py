@@ -152,3 +152,27 @@ def test_vcycle_full_size_nine_cell_and_weighted(form):
         ref = multigrid.vcycle(hier, b)
         z = op.vcycle(torch.from_numpy(b).cuda()).cpu().numpy()
     assert _rel(z, ref) <= 1e-10
+
+
+def test_batch_of_four_c384():
+    """C384 x 70 with four right-hand sides (61,931,520 unknowns each, 7
+    levels): float32-MG CG to 1e-6; true float64 residuals by the oracle's
+    apply, and each member equal to its own solve, bit for bit (the batch and
+    the single solves choose the streamed kernel variants on different levels,
+    which changes no arithmetic)."""
+    from paper_2002_00756_amd import Operator
+    w = workloads.C384x70
+    print("C384x70 batch of 4", flush=True)
+    kh, kv, delta = workloads.workload_coefficients(w)
+    op = Operator(w.N, w.nz, kh, kv, delta, w.nlevels, precision="fp32", max_batch=4)
+    b = workloads.rhs(w.N, w.nz, 4, seed=13)
+    bd = torch.from_numpy(b).cuda()
+    res = op.solve(bd, rtol=1e-6)
+    assert res.converged
+    lev = mesh.Level(w.N)
+    for i in (0, 3):
+        x = res.x[i].cpu().numpy()
+        true = np.linalg.norm(b[i] - helmholtz.apply(lev, kh, kv, delta, x)) / np.linalg.norm(b[i])
+        assert true <= 1.05e-6
+        single = op.solve(bd[i], rtol=1e-6)
+        assert single.iters[0] == res.iters[i] and torch.equal(single.x, res.x[i])
