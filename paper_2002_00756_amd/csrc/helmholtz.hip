@@ -1027,9 +1027,12 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     HH_CHECK(hipMemcpyAsync(h->sc, h->hsc, size_t(batch) * kScal * sizeof(double),
                             hipMemcpyHostToDevice, s));
     // x = 0, r = b, ||b||^2
-    hipLaunchKernelGGL(k_cg_init, tgrid, blk, 0, s, b, x, h->r, r32, bicg ? h->r0 : nullptr,
-                       v0.ncol, h->nz, v0.nvp, st);
+    // (CG writes x in its first update; the right-hand sides that do not
+    // start are zeroed after the norms)
+    hipLaunchKernelGGL(k_cg_init, tgrid, blk, 0, s, b, bicg ? x : nullptr, h->r, r32,
+                       bicg ? h->r0 : nullptr, v0.ncol, h->nz, v0.nvp, st);
     hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBB), ntile32, 0);
+    if (!bicg) hipLaunchKernelGGL(k_cg_zero_idle, tgrid, blk, 0, s, x, v0.ncol, h->nz, st);
     if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
     std::vector<int> need(batch, 1);
     if (int e = wait_published(h, s, need, 0)) return e;
@@ -1089,12 +1092,13 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
                            0);
         // x += alpha p, r -= alpha q, ||r||^2 and the convergence flags, published
+        const int first = iter == 1 ? 1 : 0;
         if (vnt)
             hipLaunchKernelGGL(k_cg_update<true>, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q,
-                               v0.ncol, h->nz, v0.nvp, st);
+                               v0.ncol, h->nz, v0.nvp, st, first);
         else
             hipLaunchKernelGGL(k_cg_update<false>, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q,
-                               v0.ncol, h->nz, v0.nvp, st);
+                               v0.ncol, h->nz, v0.nvp, st, first);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRR), ntile32, iter);
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
         if (int e = wait_published(h, s, was_active, iter)) return e;

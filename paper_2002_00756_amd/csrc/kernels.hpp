@@ -1146,8 +1146,9 @@ __device__ __forceinline__ TileGrid tile_grid(int ncol) {
 }
 constexpr int kTileGroups = kBlock / kTile;
 
-// x = 0, r = b, r32 = float(b), r0 = b (b and x in the ABI layout; r32 and
-// r0 may be null); partial ||b||^2 per tile.
+// x = 0, r = b, r32 = float(b), r0 = b (b and x in the ABI layout; x, r32
+// and r0 may be null: CG writes x in its first update, see k_cg_update);
+// partial ||b||^2 per tile.
 __global__ void __launch_bounds__(kBlock)
 k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restrict__ r,
           float* __restrict__ r32, double* __restrict__ r0, int ncol, int nz, int nvp,
@@ -1160,7 +1161,7 @@ k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restri
         const int64_t ia = t.rhs * n + t.c, it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
         for (int k = t.g; k < nz; k += kTileGroups) {
             const double v = b[ia + int64_t(k) * ncol];
-            x[ia + int64_t(k) * ncol] = 0.0;
+            if (x) x[ia + int64_t(k) * ncol] = 0.0;
             r[it + kTile * k] = v;
             if (r32) r32[it + kTile * k] = float(v);
             if (r0) r0[it + kTile * k] = v;
@@ -1171,15 +1172,26 @@ k_cg_init(const double* __restrict__ b, double* __restrict__ x, double* __restri
     store_partial(st, t.rhs, t.tile, s, 0.0, false);
 }
 
-// x += alpha p (x in the ABI layout); r -= alpha q; r32 = float(r); partial
-// ||r||^2 per tile. NT (vectors far larger than the last-level cache): x, q
-// and r, whose next reader comes after a whole V-cycle, bypass the cache, so
-// that it keeps r32 for the first smoothing sweep.
+// x = 0 for the right-hand sides that do not start (b = 0 or not finite);
+// the others get x in the first CG update.
+__global__ void __launch_bounds__(kBlock)
+k_cg_zero_idle(double* __restrict__ x, int ncol, int nz, CgState st) {
+    const TileGrid t = tile_grid(ncol);
+    if (st.active[t.rhs] || !t.valid) return;
+    const int64_t ia = t.rhs * int64_t(nz) * ncol + t.c;
+    for (int k = t.g; k < nz; k += kTileGroups) x[ia + int64_t(k) * ncol] = 0.0;
+}
+
+// x += alpha p (x in the ABI layout; first: x = alpha p, x not read);
+// r -= alpha q; r32 = float(r); partial ||r||^2 per tile. NT (vectors far
+// larger than the last-level cache): x, q and r, whose next reader comes
+// after a whole V-cycle, bypass the cache, so that it keeps r32 for the first
+// smoothing sweep.
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
             const double* __restrict__ p, const double* __restrict__ q, int ncol, int nz, int nvp,
-            CgState st) {
+            CgState st, int first) {
     __shared__ double sh[kBlock / 64];
     const TileGrid t = tile_grid(ncol);
     if (!st.active[t.rhs]) return;
@@ -1192,7 +1204,7 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ 
             const int64_t o = it + kTile * k;
             double* xk = x + ia + int64_t(k) * ncol;
             const double v = stream_load<NT>(r + o) - alpha * stream_load<NT>(q + o);
-            stream_store<NT>(xk, stream_load<NT>(xk) + alpha * p[o]);
+            stream_store<NT>(xk, first ? alpha * p[o] : stream_load<NT>(xk) + alpha * p[o]);
             stream_store<NT>(r + o, v);
             if (r32) r32[o] = float(v);
             acc += v * v;
