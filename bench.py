@@ -62,13 +62,14 @@ def vcycle_words(L, n_pre, n_post, n_coarse):
 
 
 def cg_bytes_per_unknown(vc_words, mixed, flexible):
-    """Algorithmic bytes per unknown of one CG iteration (outer loop in float64)."""
+    """Algorithmic bytes per unknown of one CG iteration (outer loop in float64).
+    The x update rides with the p update, which reads p once for both."""
     apply_dot = 6 * 8                      # p, kh[2], kv, delta read; q written
-    update = 4 * 8 + 2 * 8 + (4 if mixed else 0)   # x, p, r, q read; x, r (, r32) written
+    update = 2 * 8 + 8 + (4 if mixed else 0)   # r, q read; r (, r32) written
     vc = vc_words * (4 if mixed else 8)
     zsz = 4 if mixed else 8
     dot = 8 + zsz + (8 if flexible else 0)
-    pupd = zsz + 8 + 8
+    pupd = zsz + 8 + 8 + 8 + 8             # z, p, x read; p, x written
     return apply_dot + update + vc + dot + pupd
 
 

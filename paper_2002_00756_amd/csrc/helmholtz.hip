@@ -123,6 +123,7 @@ struct helmholtz_s {
     int pstride = 0;
     double* sc = nullptr;     // [B][8] scalars
     int* active = nullptr;    // [B]
+    int* upd = nullptr;       // [B] CG: the last residual update included the rhs
     int* flags = nullptr;     // set-up validation bits
     // pinned, host-coherent mirror written by the device: scalars, flags,
     // per-RHS sequence numbers; plus the set-up flags
@@ -201,6 +202,7 @@ void layout(helmholtz_s* h, Carver& cv) {
     h->partial2 = cv.take<double>(size_t(B) * h->pstride);
     h->sc = cv.take<double>(size_t(B) * kScal);
     h->active = cv.take<int>(size_t(B));
+    h->upd = cv.take<int>(size_t(B));
     h->flags = cv.take<int>(4);
 }
 
@@ -278,7 +280,7 @@ void prof_end(const helmholtz_s* h, int kernel, double bytes, hipStream_t s) {
 }
 
 CgState cg_state(const helmholtz_s* h) {
-    return CgState{h->partial, h->partial2, h->pstride, h->sc, h->active,
+    return CgState{h->partial, h->partial2, h->pstride, h->sc, h->active, h->upd,
                    h->hsc,     h->hact,     h->hseq};
 }
 
@@ -1066,10 +1068,11 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         if (mixed) vnt ? go(k_dot_rz<float, true>, z32) : go(k_dot_rz<float, false>, z32);
         else vnt ? go(k_dot_rz<double, true>, h->z) : go(k_dot_rz<double, false>, h->z);
     };
-    auto p_update = [&](int init) {
+    // p = z + beta p, with the x update owed from the last iteration (xmode)
+    auto p_update = [&](int init, int xmode) {
         auto go = [&](auto kern, auto z) {
-            hipLaunchKernelGGL(kern, red, blk, 0, s, z, h->p, n, kRedBlocks, h->sc, h->active,
-                               init);
+            hipLaunchKernelGGL(kern, tgrid, blk, 0, s, z, h->p, x, v0.ncol, h->nz, v0.nvp, st,
+                               init, xmode);
         };
         if (mixed) vnt ? go(k_p_update<float, true>, z32) : go(k_p_update<float, false>, z32);
         else vnt ? go(k_p_update<double, true>, h->z) : go(k_p_update<double, false>, h->z);
@@ -1079,7 +1082,16 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
     dot_rz(nullptr);
     hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRho), kRedBlocks, 0);
-    p_update(1);
+    p_update(1, kXNone);
+    // the owed x update where the iteration stops (see k_cg_x)
+    auto x_update = [&](int xmode, int only_done) {
+        if (vnt)
+            hipLaunchKernelGGL(k_cg_x<true>, tgrid, blk, 0, s, x, h->p, v0.ncol, h->nz, v0.nvp,
+                               st, xmode, only_done);
+        else
+            hipLaunchKernelGGL(k_cg_x<false>, tgrid, blk, 0, s, x, h->p, v0.ncol, h->nz, v0.nvp,
+                               st, xmode, only_done);
+    };
 
     const int ntile0 = (h->lev[0].ncol + kBlock - 1) / kBlock;
     const int nkc0 = (h->nz + kApplyChunk - 1) / kApplyChunk;
@@ -1091,18 +1103,19 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         launch_apply<double>(h, 0, h->p, h->q, batch, kDotXY, h->active, s);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinAlpha), ntile0 * nkc0,
                            0);
-        // x += alpha p, r -= alpha q, ||r||^2 and the convergence flags, published
-        const int first = iter == 1 ? 1 : 0;
+        // r -= alpha q, ||r||^2 and the convergence flags, published; the
+        // matching x += alpha p is owed (applied with the next p update, or
+        // by x_update where the iteration stops)
         if (vnt)
-            hipLaunchKernelGGL(k_cg_update<true>, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q,
-                               v0.ncol, h->nz, v0.nvp, st, first);
+            hipLaunchKernelGGL(k_cg_update<true>, tgrid, blk, 0, s, h->r, r32, h->q, v0.ncol,
+                               h->nz, v0.nvp, st);
         else
-            hipLaunchKernelGGL(k_cg_update<false>, tgrid, blk, 0, s, x, h->r, r32, h->p, h->q,
-                               v0.ncol, h->nz, v0.nvp, st, first);
+            hipLaunchKernelGGL(k_cg_update<false>, tgrid, blk, 0, s, h->r, r32, h->q, v0.ncol,
+                               h->nz, v0.nvp, st);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRR), ntile32, iter);
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
         if (int e = wait_published(h, s, was_active, iter)) return e;
-        bool still = false;
+        bool still = false, some_done = false;
         for (int i = 0; i < batch; ++i) {
             if (!was_active[i]) continue;
             it[i] = iter;
@@ -1110,18 +1123,21 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
             if (!std::isfinite(rr)) return finish(HELMHOLTZ_ENONFINITE);
             rel[i] = std::sqrt(rr / bnorm2[i]);
             still = still || h->hact[i];
+            some_done = some_done || !h->hact[i];
         }
-        if (!still) break;
-        if (iter >= maxiter) {
-            status = HELMHOLTZ_NOT_CONVERGED;
+        const int xmode = iter == 1 ? kXSet : kXAdd;  // x is first written here
+        if (!still || iter >= maxiter) {
+            x_update(xmode, 0);
+            if (still) status = HELMHOLTZ_NOT_CONVERGED;
             break;
         }
-        // z = M r, beta, p = z + beta p
+        if (some_done) x_update(xmode, 1);
+        // z = M r, beta, p = z + beta p (with the owed x update)
         if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
         dot_rz(flex ? h->q : nullptr);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st,
                            int(flex ? kFinBetaFlex : kFinBeta), kRedBlocks, 0);
-        p_update(0);
+        p_update(0, xmode);
     }
     // the caller may read x as soon as this returns on the host
     HH_CHECK(hipStreamSynchronize(s));

@@ -461,6 +461,7 @@ struct CgState {
     int pstride;
     double* sc;        // [B][8]
     int* active;       // [B]
+    int* upd;          // [B] CG: the last residual update included the rhs
     double* hsc;       // host mirror [B][8]
     int* hact;         // host mirror [B]
     int* hseq;         // host mirror [B]
@@ -523,6 +524,8 @@ k_finalize(CgState st, int mode, int cnt, int seq) {
     }
     if (threadIdx.x != 0) return;
     double* v = st.sc + rhs * kScal;
+    // CG: an x update is owed exactly where r was updated
+    if (mode == kFinRR) st.upd[rhs] = live ? 1 : 0;
     switch (live ? mode : -1) {
         case kFinBB:
             v[kBB] = t1;
@@ -1182,29 +1185,26 @@ k_cg_zero_idle(double* __restrict__ x, int ncol, int nz, CgState st) {
     for (int k = t.g; k < nz; k += kTileGroups) x[ia + int64_t(k) * ncol] = 0.0;
 }
 
-// x += alpha p (x in the ABI layout; first: x = alpha p, x not read);
-// r -= alpha q; r32 = float(r); partial ||r||^2 per tile. NT (vectors far
-// larger than the last-level cache): x, q and r, whose next reader comes
-// after a whole V-cycle, bypass the cache, so that it keeps r32 for the first
-// smoothing sweep.
+// r -= alpha q; r32 = float(r); partial ||r||^2 per tile. The matching
+// x += alpha p is owed: k_p_update applies it as it replaces p (one read of
+// p for both), k_cg_x where the iteration stops. NT (vectors far larger than
+// the last-level cache): q and r, whose next reader comes after a whole
+// V-cycle, bypass the cache, so that it keeps r32 for the first smoothing
+// sweep.
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
-k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ r32,
-            const double* __restrict__ p, const double* __restrict__ q, int ncol, int nz, int nvp,
-            CgState st, int first) {
+k_cg_update(double* __restrict__ r, float* __restrict__ r32, const double* __restrict__ q,
+            int ncol, int nz, int nvp, CgState st) {
     __shared__ double sh[kBlock / 64];
     const TileGrid t = tile_grid(ncol);
     if (!st.active[t.rhs]) return;
     const double alpha = st.sc[t.rhs * kScal + kAlpha];
-    const int64_t n = int64_t(nz) * ncol;
     double acc = 0.0;
     if (t.valid) {
-        const int64_t ia = t.rhs * n + t.c, it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
+        const int64_t it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
         for (int k = t.g; k < nz; k += kTileGroups) {
             const int64_t o = it + kTile * k;
-            double* xk = x + ia + int64_t(k) * ncol;
             const double v = stream_load<NT>(r + o) - alpha * stream_load<NT>(q + o);
-            stream_store<NT>(xk, first ? alpha * p[o] : stream_load<NT>(xk) + alpha * p[o]);
             stream_store<NT>(r + o, v);
             if (r32) r32[o] = float(v);
             acc += v * v;
@@ -1212,6 +1212,29 @@ k_cg_update(double* __restrict__ x, double* __restrict__ r, float* __restrict__ 
     }
     const double s = block_sum(acc, sh);
     store_partial(st, t.rhs, t.tile, s, 0.0, false);
+}
+
+// The x update of CG (x in the ABI layout): kXSet x = alpha p (the first
+// iteration: x is not read), kXAdd x += alpha p.
+enum { kXNone = 0, kXSet = 1, kXAdd = 2 };
+
+// The owed x update where the iteration stops: for the right-hand sides that
+// the last residual update included (upd) and, with only_done, that have
+// converged in it. NT: x bypasses the cache.
+template <bool NT>
+__global__ void __launch_bounds__(kBlock)
+k_cg_x(double* __restrict__ x, const double* __restrict__ p, int ncol, int nz, int nvp,
+       CgState st, int xmode, int only_done) {
+    const TileGrid t = tile_grid(ncol);
+    if (!t.valid || !st.upd[t.rhs] || (only_done && st.active[t.rhs])) return;
+    const double alpha = st.sc[t.rhs * kScal + kAlpha];
+    const int64_t ia = t.rhs * int64_t(nz) * ncol + t.c;
+    const int64_t it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
+    for (int k = t.g; k < nz; k += kTileGroups) {
+        double* xk = x + ia + int64_t(k) * ncol;
+        const double ap = alpha * p[it + kTile * k];
+        stream_store<NT>(xk, xmode == kXSet ? ap : stream_load<NT>(xk) + ap);
+    }
 }
 
 // Layout conversion between the ABI layout and the tiled one, with a cast.
@@ -1258,22 +1281,34 @@ k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __
     store_partial(st, rhs, blk, s1, s2, q != nullptr);
 }
 
-// p = z + beta p (init: p = z). NT: z, read for the last time, bypasses the
-// cache, which keeps p for the apply that follows.
+// p = z + beta p (init: p = z) for the right-hand sides still iterating and,
+// first, the x update owed from the last iteration (xmode), with the p about
+// to be replaced: one read of p for both. One workgroup per (right-hand side,
+// tile); x in the ABI layout. NT: z (read for the last time) and x bypass
+// the cache, which keeps p for the apply that follows.
 template <typename Z, bool NT>
 __global__ void __launch_bounds__(kBlock)
-k_p_update(const Z* __restrict__ z, double* __restrict__ p, int64_t n, int nblk,
-           const double* __restrict__ sc, const int* __restrict__ active, int init) {
-    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
-    if (!active[rhs]) return;
-    const double beta = init ? 0.0 : sc[rhs * kScal + kBeta];
-    int64_t i0, i1;
-    grid_range(n, nblk, blk, i0, i1);
-    const int64_t off = int64_t(rhs) * n;
-#pragma unroll 4
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        const double zv = double(stream_load<NT>(z + off + i));
-        p[off + i] = init ? zv : zv + beta * p[off + i];
+k_p_update(const Z* __restrict__ z, double* __restrict__ p, double* __restrict__ x, int ncol,
+           int nz, int nvp, CgState st, int init, int xmode) {
+    const TileGrid t = tile_grid(ncol);
+    if (!t.valid || !st.active[t.rhs]) return;
+    const double beta = init ? 0.0 : st.sc[t.rhs * kScal + kBeta];
+    const double alpha = xmode != kXNone ? st.sc[t.rhs * kScal + kAlpha] : 0.0;
+    const int64_t ia = t.rhs * int64_t(nz) * ncol + t.c;
+    const int64_t it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
+    for (int k = t.g; k < nz; k += kTileGroups) {
+        const int64_t o = it + kTile * k;
+        const double zv = double(stream_load<NT>(z + o));
+        if (init) {
+            p[o] = zv;
+            continue;
+        }
+        const double pv = p[o];
+        if (xmode != kXNone) {
+            double* xk = x + ia + int64_t(k) * ncol;
+            stream_store<NT>(xk, xmode == kXSet ? alpha * pv : stream_load<NT>(xk) + alpha * pv);
+        }
+        p[o] = zv + beta * pv;
     }
 }
 

@@ -132,9 +132,11 @@ def test_bench_byte_model():
     assert bench.vcycle_words(2, 2, 2, 4) == 31.5 + 25.0 / 4
     L6 = 31.5 * sum(4.0 ** -l for l in range(5)) + 25.0 / 4 ** 5
     assert abs(bench.vcycle_words(6, 2, 2, 4) - L6) < 1e-12
-    # one CG iteration: apply+dot 48, update 52 (mixed) / 48, dot 12 / 16, p-update 20 / 24
-    assert bench.cg_bytes_per_unknown(0.0, True, False) == 48 + 52 + 12 + 20
-    assert bench.cg_bytes_per_unknown(0.0, False, False) == 48 + 48 + 16 + 24
+    # one CG iteration: apply+dot 48, residual update 28 (mixed: r, q read; r,
+    # r32 written) / 24, dot 12 / 16, p and x update 36 / 40 (z, p, x read;
+    # p, x written)
+    assert bench.cg_bytes_per_unknown(0.0, True, False) == 48 + 28 + 12 + 36
+    assert bench.cg_bytes_per_unknown(0.0, False, False) == 48 + 24 + 16 + 40
 
 
 def test_bench_bicgstab_byte_model():
