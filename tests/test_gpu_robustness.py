@@ -155,3 +155,25 @@ def test_batch_members_converging_at_different_iterations(precision):
         single = op.solve(torch.from_numpy(b[i]).cuda(), rtol=1e-8)
         assert single.iters[0] == res.iters[i]
         assert torch.equal(single.x, res.x[i])
+
+
+def test_cg_first_iteration_stop_and_batch_maxiter():
+    """The owed x update where the iteration stops: a solve that converges in
+    its first iteration (x is written, not added to) against the oracle, and a
+    batch stopped by maxiter against the single solves, bit for bit."""
+    from paper_2002_00756_amd import Operator
+    print("CG stops at iteration 1 and at maxiter", flush=True)
+    hier, (kh, kv, delta) = _hier(12, 10, 3)
+    for precision in ("fp64", "fp32"):
+        op = Operator(12, 10, kh, kv, delta, 3, precision=precision, max_batch=2)
+        b = workloads.rhs(12, 10, 2, seed=21)
+        bd = torch.from_numpy(b).cuda()
+        res = op.solve(bd[0], rtol=0.9)
+        ref = krylov.solve(hier, b[0], rtol=0.9)
+        assert res.iters[0] == ref.iters == 1
+        assert np.linalg.norm(res.x.cpu().numpy() - ref.x) <= 1e-5 * np.linalg.norm(ref.x)
+        both = op.solve(bd, rtol=1e-14, maxiter=3)
+        assert not both.converged and list(both.iters) == [3, 3]
+        for i in range(2):
+            single = op.solve(bd[i], rtol=1e-14, maxiter=3)
+            assert torch.equal(single.x, both.x[i])
