@@ -37,7 +37,9 @@
  * Memory. The library never allocates device memory: the caller passes one
  * workspace of helmholtz_workspace_bytes(cfg) bytes to helmholtz_create and
  * keeps it alive until helmholtz_destroy. The handle itself lives in host
- * memory (plus a small pinned host buffer for the solver's scalars).
+ * memory (plus a small pinned host buffer for the solver's scalars). The one
+ * exception is a static device array of HELMHOLTZ_NOALLOC_SCRATCH_BYTES per
+ * GPU, loaded with the library, that only helmholtz_vcycle_noalloc uses.
  * Calls on one handle must not overlap (a handle is not thread-safe and its
  * workspace is shared by all its calls).
  *
@@ -66,7 +68,9 @@ enum {
                                     > max_batch, or sizes beyond 32-bit indexing   */
     HELMHOLTZ_EWORKSPACE = -3,   /* workspace NULL, too small or misaligned        */
     HELMHOLTZ_ENONFINITE = -4,   /* NaN/Inf in coefficients or in a solve          */
-    HELMHOLTZ_EHIP = -5          /* a HIP runtime call or kernel launch failed     */
+    HELMHOLTZ_EHIP = -5,         /* a HIP runtime call or kernel launch failed     */
+    HELMHOLTZ_ESCRATCH = -6      /* helmholtz_vcycle_noalloc: the level vectors do
+                                    not fit HELMHOLTZ_NOALLOC_SCRATCH_BYTES          */
 };
 
 enum { HELMHOLTZ_FP64 = 0, HELMHOLTZ_FP32 = 1 };               /* V-cycle precision   */
@@ -163,6 +167,28 @@ int helmholtz_apply(helmholtz_t h, const double* x, double* y, int32_t batch,
  * b and x [batch][nz][ncol] float64, must not overlap. Asynchronous. */
 int helmholtz_vcycle(helmholtz_t h, const double* b, double* x, int32_t batch,
                      helmholtz_stream_t stream);
+
+/* helmholtz_vcycle for callers that cannot allocate device memory at call
+ * time (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same V-cycle, with the same kernels and the same
+ * result bit for bit, but its level vectors (right-hand side, iterate and
+ * Jacobi partner of every level, 3 * batch * nz * ncol_l values of the
+ * handle's mg_precision per level l, columns padded to multiples of 32) live
+ * in a static device array of HELMHOLTZ_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends, instead of in
+ * the workspace. The call allocates and frees nothing (with the kernel
+ * timing hook off it creates no HIP objects either). Nothing in the scratch
+ * needs to start at zero; it keeps the last call's contents. Every call on
+ * one GPU shares that GPU's array, so calls that overlap on one GPU (any
+ * handle, any stream) race and must be serialised by the caller.
+ * The calling thread's current device must be the one the handle was created
+ * on (else HELMHOLTZ_EINVAL). Returns HELMHOLTZ_ESCRATCH, launching nothing,
+ * when the level vectors exceed the array: e.g. C96 x 30 with 5 levels fits
+ * at batch 1 in float64 and at batch 2 in float32, C192 x 70 does not.
+ * b and x [batch][nz][ncol] float64, must not overlap. Asynchronous. */
+#define HELMHOLTZ_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int helmholtz_vcycle_noalloc(helmholtz_t h, const double* b, double* x, int32_t batch,
+                             helmholtz_stream_t stream);
 
 /* Same V-cycle entirely in float32 (coefficients, vectors and accumulation).
  * b and x [batch][nz][ncol] float32, must not overlap. Asynchronous. */

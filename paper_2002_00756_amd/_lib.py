@@ -13,11 +13,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhelmholtz.so")
 
 OK, NOT_CONVERGED = 0, 1
-EINVAL, ESHAPE, EWORKSPACE, ENONFINITE, EHIP = -1, -2, -3, -4, -5
+EINVAL, ESHAPE, EWORKSPACE, ENONFINITE, EHIP, ESCRATCH = -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
 CG_STANDARD, CG_FLEXIBLE, BICGSTAB = 0, 1, 2
 NZ_MAX = 120
 WORKSPACE_ALIGN = 256
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 # Every function the header declares, with (restype, argtypes).
 _c_int, _c_size, _vp, _dp = ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p
@@ -50,6 +51,7 @@ SIGNATURES = {
     "helmholtz_apply": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_vcycle": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_vcycle_f32": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
+    "helmholtz_vcycle_noalloc": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_solve": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
                                  _i32p, _f64p, _vp]),
     "helmholtz_solve_adjoint": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,

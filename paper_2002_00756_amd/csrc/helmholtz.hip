@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -21,6 +22,7 @@ using namespace hh;
 namespace {
 
 constexpr int kRedBlocks = 2048;  // partial sums per right-hand side for vector reductions
+constexpr int kMaxLevels = 20;    // deepest hierarchy a configuration may ask for
 constexpr int kApplyChunk = 4;   // vertical levels per thread in apply / residual kernels
 constexpr int kSmallSweepCols = 5000;  // levels below this use narrow sweep tiles
 
@@ -38,6 +40,16 @@ struct LevelData {
     T* b = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
     T* x = nullptr;   // [B][nvp]   level >= 1 (and level 0 for float32)
     T* t = nullptr;   // [B][nvp]   ping-pong partner of x
+};
+
+// The vectors one V-cycle works in, per level: right-hand side b, iterate x
+// and its Jacobi ping-pong partner t. They come from the handle's workspace
+// or, for the allocation-free entry point, from the static scratch array.
+template <typename T>
+struct VBufs {
+    T* b[kMaxLevels] = {};
+    T* x[kMaxLevels] = {};
+    T* t[kMaxLevels] = {};
 };
 
 struct Level {
@@ -69,7 +81,8 @@ struct Carver {
 
 bool config_ok(const helmholtz_config* c) {
     if (!c) return false;
-    if (c->N < 1 || c->nz < 1 || c->nz > HELMHOLTZ_NZ_MAX || c->nlevels < 1 || c->nlevels > 20)
+    if (c->N < 1 || c->nz < 1 || c->nz > HELMHOLTZ_NZ_MAX || c->nlevels < 1 ||
+        c->nlevels > kMaxLevels)
         return false;
     if (c->n_pre < 0 || c->n_post < 0 || c->n_coarse < 1) return false;
     if (!(c->omega > 0.0 && c->omega <= 1.5)) return false;
@@ -93,6 +106,40 @@ int shape_error(const helmholtz_config* c) {
     // two kh planes unsigned); batch offsets are 64-bit
     if (2 * ncol >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
     if (int64_t(c->nz) * ncolp >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
+    return HELMHOLTZ_OK;
+}
+
+}  // namespace
+
+// ---- allocation-free V-cycle: static scratch -------------------------------
+// helmholtz_vcycle_noalloc keeps its level vectors in this file-scope device
+// array instead of the workspace. Each GPU holds its own copy until the
+// process ends; host code reaches it only through the address
+// hipGetSymbolAddress returns for the device that is current (the array's
+// name is a host-side stand-in, not a device address).
+constexpr size_t kScratchBytes = HELMHOLTZ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the scratch array on the current device, looked up once per
+// device; `dev` receives the device index.
+int scratch_of_current_device(unsigned char** out, int* dev) {
+    *out = nullptr;
+    if (hipGetDevice(dev) != hipSuccess) return HELMHOLTZ_EHIP;
+    if (*dev < 0 || *dev >= kMaxDevices) return HELMHOLTZ_EHIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[*dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p)
+            return HELMHOLTZ_EHIP;
+        g_scratch_ptr[*dev] = static_cast<unsigned char*>(p);
+    }
+    *out = g_scratch_ptr[*dev];
     return HELMHOLTZ_OK;
 }
 
@@ -141,6 +188,13 @@ struct helmholtz_s {
     };
     bool prof_on = false;
     mutable Prof prof[HELMHOLTZ_PROF_COUNT];
+    // V-cycle vectors in the workspace (float64: level 0 comes from the caller)
+    VBufs<double> vb64;
+    VBufs<float> vb32;
+    // this device's copy of the static scratch array (allocation-free entry
+    // point) and the device the handle was created on
+    unsigned char* scratch = nullptr;
+    int device = -1;
 };
 
 namespace {
@@ -182,6 +236,12 @@ void layout(helmholtz_s* h, Carver& cv) {
         v.f.b = cv.take<float>(size_t(B) * nv);
         v.f.x = cv.take<float>(size_t(B) * nv);
         v.f.t = cv.take<float>(size_t(B) * nv);
+        h->vb64.b[l] = v.d.b;
+        h->vb64.x[l] = v.d.x;
+        h->vb64.t[l] = v.d.t;
+        h->vb32.b[l] = v.f.b;
+        h->vb32.x[l] = v.f.x;
+        h->vb32.t[l] = v.f.t;
     }
     const size_t nb = size_t(B) * size_t(h->nvp);
     h->r = cv.take<double>(nb);
@@ -296,9 +356,9 @@ LevelView<T> view(const helmholtz_s* h, int l) {
 }
 
 template <typename T>
-LevelData<T>& data(helmholtz_s* h, int l) {
-    if constexpr (std::is_same<T, double>::value) return h->lev[l].d;
-    else return h->lev[l].f;
+const VBufs<T>& ws_bufs(const helmholtz_s* h) {
+    if constexpr (std::is_same<T, double>::value) return h->vb64;
+    else return h->vb32;
 }
 
 // ---- sweep launch: compile-time bound on levels per thread ---------------
@@ -538,13 +598,13 @@ T* write_dst(const helmholtz_s* h, int l, int j, T* out, T* tmp) {
     return ((level_writes(h, l) - 1 - j) % 2 == 0) ? out : tmp;
 }
 
-// Level l smooths b_l into out_l (Algorithm 1), using tmp_l as the Jacobi
-// ping-pong partner.
+// Level l smooths b_l into out_l (Algorithm 1), using V.t[l] as the Jacobi
+// ping-pong partner and V.b, V.x of the coarser levels.
 template <typename T>
-void vcycle_level(helmholtz_s* h, int l, const T* b, T* out, int batch, const int* active,
-                  hipStream_t s) {
+void vcycle_level(helmholtz_s* h, const VBufs<T>& V, int l, const T* b, T* out, int batch,
+                  const int* active, hipStream_t s) {
     const helmholtz_config& cfg = h->cfg;
-    T* tmp = data<T>(h, l).t;
+    T* tmp = V.t[l];
     const int W = level_writes(h, l);
     if (l == h->L - 1) {
         const T* prev = nullptr;
@@ -562,22 +622,23 @@ void vcycle_level(helmholtz_s* h, int l, const T* b, T* out, int batch, const in
         launch_sweep<T>(h, l, j == 0 ? kZero : kPlain, b, prev, nullptr, dst, batch, active, s);
         prev = dst;
     }
-    LevelData<T>& c = data<T>(h, l + 1);
-    launch_resid_restrict<T>(h, l, b, prev, c.b, batch, active, s);
-    vcycle_level<T>(h, l + 1, c.b, c.x, batch, active, s);
+    T* cb = V.b[l + 1];
+    T* cx = V.x[l + 1];
+    launch_resid_restrict<T>(h, l, b, prev, cb, batch, active, s);
+    vcycle_level<T>(h, V, l + 1, cb, cx, batch, active, s);
     if (cfg.n_post == 0) {
         T* dst = write_dst<T>(h, l, j, out, tmp);
         const Level& v = h->lev[l];
         const int64_t total = int64_t(batch) * h->nz * v.ncol;
         hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(total)), dim3(kBlock), 0, s, v.ncol,
-                           h->nz, v.nvp, h->lev[l + 1].nvp, v.parent, prev, c.x, dst, total);
+                           h->nz, v.nvp, h->lev[l + 1].nvp, v.parent, prev, cx, dst, total);
         return;
     }
     for (int i = 0; i < cfg.n_post; ++i, ++j) {
         T* dst = write_dst<T>(h, l, j, out, tmp);
         int mode = kPlain;
         if (i == 0) mode = prev ? kProlong : kProlongZero;
-        launch_sweep<T>(h, l, mode, b, prev, c.x, dst, batch, active, s);
+        launch_sweep<T>(h, l, mode, b, prev, cx, dst, batch, active, s);
         prev = dst;
     }
 }
@@ -608,10 +669,9 @@ void retile(const helmholtz_s* h, const S* src, D* dst, int batch, hipStream_t s
 int precondition(helmholtz_s* h, const double* r, double* z, int batch, const int* active,
                  hipStream_t s) {
     if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
-        vcycle_level<double>(h, 0, r, z, batch, active, s);
+        vcycle_level<double>(h, h->vb64, 0, r, z, batch, active, s);
     } else {
-        LevelData<float>& f = h->lev[0].f;
-        vcycle_level<float>(h, 0, f.b, f.x, batch, active, s);
+        vcycle_level<float>(h, h->vb32, 0, h->vb32.b[0], h->vb32.x[0], batch, active, s);
     }
     return last_error();
 }
@@ -651,13 +711,13 @@ int wait_published(helmholtz_s* h, hipStream_t s, const std::vector<int>& need, 
 int precondition_into(helmholtz_s* h, const double* u, double* out, int batch, const int* active,
                       hipStream_t s) {
     if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
-        vcycle_level<double>(h, 0, u, out, batch, active, s);
+        vcycle_level<double>(h, h->vb64, 0, u, out, batch, active, s);
     } else {
-        LevelData<float>& f = h->lev[0].f;
+        const VBufs<float>& V = h->vb32;
         const int64_t n = int64_t(batch) * h->nvp;
-        convert<double, float>(u, f.b, n, s);
-        vcycle_level<float>(h, 0, f.b, f.x, batch, active, s);
-        convert<float, double>(f.x, out, n, s);
+        convert<double, float>(u, V.b[0], n, s);
+        vcycle_level<float>(h, V, 0, V.b[0], V.x[0], batch, active, s);
+        convert<float, double>(V.x[0], out, n, s);
     }
     return last_error();
 }
@@ -726,6 +786,33 @@ int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
                 const double* kv2, const double* delta, const double* sw, void* workspace,
                 size_t workspace_bytes, helmholtz_stream_t stream_, helmholtz_t* out);
 
+// Level vectors b, x, t of every level for `batch` right-hand sides, carved
+// from `base`; returns the bytes they take.
+template <typename T>
+size_t carve_levels(const helmholtz_s* h, uintptr_t base, int batch, VBufs<T>& V) {
+    Carver cv{base};
+    for (int l = 0; l < h->L; ++l) {
+        const size_t nv = size_t(batch) * size_t(h->lev[l].nvp);
+        V.b[l] = cv.take<T>(nv);
+        V.x[l] = cv.take<T>(nv);
+        V.t[l] = cv.take<T>(nv);
+    }
+    return cv.off;
+}
+
+// One V-cycle from the ABI layout to the ABI layout with the level vectors in
+// the static scratch array (helmholtz_vcycle_noalloc).
+template <typename T>
+int vcycle_in_scratch(helmholtz_s* h, const double* b, double* x, int batch, hipStream_t s) {
+    VBufs<T> V;
+    if (carve_levels<T>(h, reinterpret_cast<uintptr_t>(h->scratch), batch, V) > kScratchBytes)
+        return HELMHOLTZ_ESCRATCH;
+    retile<double, T, true>(h, b, V.b[0], batch, s);
+    vcycle_level<T>(h, V, 0, V.b[0], V.x[0], batch, nullptr, s);
+    retile<T, double, false>(h, V.x[0], x, batch, s);
+    return last_error();
+}
+
 // Weighted handles run the calls that take H^T with the transposed kernels.
 struct AdjointScope {
     helmholtz_s* h;
@@ -757,6 +844,8 @@ const char* helmholtz_strerror(int code) {
         case HELMHOLTZ_EWORKSPACE: return "workspace missing, too small or misaligned";
         case HELMHOLTZ_ENONFINITE: return "non-finite value (NaN or Inf)";
         case HELMHOLTZ_EHIP: return "HIP runtime error";
+        case HELMHOLTZ_ESCRATCH:
+            return "level vectors exceed the static scratch of the allocation-free entry point";
         default: return "unknown error code";
     }
 }
@@ -832,6 +921,7 @@ int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
         helmholtz_destroy(h);
         return code;
     };
+    if (int e = scratch_of_current_device(&h->scratch, &h->device)) return fail(e);
     // host-coherent pinned memory: the device publishes the CG scalars here
     if (hipHostMalloc(reinterpret_cast<void**>(&h->hsc),
                       size_t(h->B) * kScal * sizeof(double) + size_t(h->B) * 2 * sizeof(int) + 16,
@@ -983,12 +1073,24 @@ int helmholtz_vcycle(helmholtz_t h, const double* b, double* x, int32_t batch,
         if (int e = precondition(h, h->r, h->z, batch, nullptr, s)) return e;
         retile<double, double, false>(h, h->z, x, batch, s);
     } else {
-        LevelData<float>& f = h->lev[0].f;
-        retile<double, float, true>(h, b, f.b, batch, s);
+        const VBufs<float>& V = h->vb32;
+        retile<double, float, true>(h, b, V.b[0], batch, s);
         if (int e = precondition(h, nullptr, nullptr, batch, nullptr, s)) return e;
-        retile<float, double, false>(h, f.x, x, batch, s);
+        retile<float, double, false>(h, V.x[0], x, batch, s);
     }
     return last_error();
+}
+
+int helmholtz_vcycle_noalloc(helmholtz_t h, const double* b, double* x, int32_t batch,
+                             helmholtz_stream_t stream) {
+    if (int e = check_batch(h, batch)) return e;
+    if (!b || !x) return HELMHOLTZ_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return HELMHOLTZ_EHIP;
+    if (dev != h->device || !h->scratch) return HELMHOLTZ_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (h->cfg.mg_precision == HELMHOLTZ_FP64) return vcycle_in_scratch<double>(h, b, x, batch, s);
+    return vcycle_in_scratch<float>(h, b, x, batch, s);
 }
 
 int helmholtz_vcycle_f32(helmholtz_t h, const float* b, float* x, int32_t batch,
@@ -996,10 +1098,10 @@ int helmholtz_vcycle_f32(helmholtz_t h, const float* b, float* x, int32_t batch,
     if (int e = check_batch(h, batch)) return e;
     if (!b || !x) return HELMHOLTZ_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    LevelData<float>& f = h->lev[0].f;
-    retile<float, float, true>(h, b, f.b, batch, s);
-    vcycle_level<float>(h, 0, f.b, f.x, batch, nullptr, s);
-    retile<float, float, false>(h, f.x, x, batch, s);
+    const VBufs<float>& V = h->vb32;
+    retile<float, float, true>(h, b, V.b[0], batch, s);
+    vcycle_level<float>(h, V, 0, V.b[0], V.x[0], batch, nullptr, s);
+    retile<float, float, false>(h, V.x[0], x, batch, s);
     return last_error();
 }
 
@@ -1015,8 +1117,8 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     const bool mixed = h->cfg.mg_precision == HELMHOLTZ_FP32;
     const bool flex = h->cfg.cg_variant == HELMHOLTZ_CG_FLEXIBLE;
     const bool bicg = h->cfg.cg_variant == HELMHOLTZ_BICGSTAB;
-    float* r32 = mixed && !bicg ? h->lev[0].f.b : nullptr;
-    float* z32 = mixed ? h->lev[0].f.x : nullptr;
+    float* r32 = mixed && !bicg ? h->vb32.b[0] : nullptr;
+    float* z32 = mixed ? h->vb32.x[0] : nullptr;
     const dim3 red(kRedBlocks * batch), blk(kBlock), fin(kFinBlock);
     const CgState st = cg_state(h);
 

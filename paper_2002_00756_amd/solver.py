@@ -170,6 +170,18 @@ class Operator:
                                           _stream_ptr(self.device)), _fn)
         return x[0] if sq else x
 
+    def vcycle_noalloc(self, b, out=None):
+        """``vcycle`` with the level vectors in the library's static scratch array
+        instead of the workspace (for callers that cannot allocate; calls on one
+        GPU must not overlap). ``out`` receives x when given (then nothing is
+        allocated here either)."""
+        b, sq = self._vec(b)
+        x = torch.empty_like(b) if out is None else out.view(b.shape)
+        _lib.check(self.lib.helmholtz_vcycle_noalloc(self._h, b.data_ptr(), x.data_ptr(),
+                                                     b.shape[0], _stream_ptr(self.device)),
+                   "helmholtz_vcycle_noalloc")
+        return x[0] if sq else x
+
     def vcycle_adjoint(self, b):
         """One V-cycle of the transposed hierarchy (the preconditioner of H^T)."""
         return self.vcycle(b, "helmholtz_vcycle_adjoint")

@@ -31,7 +31,7 @@ def _declared_functions():
 def test_every_declared_symbol_is_exported(lib):
     from paper_2002_00756_amd import _lib
     names = _declared_functions()
-    assert len(names) == 19
+    assert len(names) == 20
     for n in names:
         assert hasattr(lib, n), n
         assert n in _lib.SIGNATURES, n
@@ -100,13 +100,14 @@ def test_create_rejects_before_touching_the_device(lib):
     assert lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(stencil=9))) > \
         lib.helmholtz_workspace_bytes(ctypes.byref(_cfg(stencil=7)))
     assert not h.value
-    for fn in ("helmholtz_apply", "helmholtz_vcycle", "helmholtz_vcycle_f32"):
+    for fn in ("helmholtz_apply", "helmholtz_vcycle", "helmholtz_vcycle_f32",
+               "helmholtz_vcycle_noalloc"):
         assert getattr(lib, fn)(None, dummy, dummy, 1, None) == _lib.EINVAL
     assert lib.helmholtz_destroy(None) == _lib.EINVAL
 
 
 def test_strerror(lib):
-    for code in (0, 1, -1, -2, -3, -4, -5, 99):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, 99):
         assert isinstance(lib.helmholtz_strerror(code), bytes)
 
 
