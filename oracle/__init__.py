@@ -29,9 +29,11 @@ Everything is float64 NumPy unless a function says otherwise.
 
 Parity status: every float64 function is pinned by the CPU tests against
 closed forms, dense linear algebra, brute force or library routines. The
-float32 emulation (``krylov.mg_preconditioner_f32``) is parity unpinned at the
-rounding level: float32 results depend on the order of operations, so there
-is no exact target; it is checked only against the float64 V-cycle within a
-bound derived from float32 rounding.
+float32 emulation (``krylov.mg_preconditioner_f32``, ``Hierarchy.astype``) is
+pinned by its parts: its coefficients bit for bit against the exact
+re-discretised values rounded once, its column solve against a float64 banded
+solver within the Thomas algorithm's forward-error bound, and the one-level
+V-cycle against its closed form within that bound. A whole float32 V-cycle
+has no bit-exact target (float32 results depend on the order of operations).
 """
 from . import mesh, helmholtz, smoother, multigrid, krylov, adjoint  # noqa: F401

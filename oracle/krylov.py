@@ -33,10 +33,13 @@ class CGResult:
     history: list
 
 
-def pcg(apply_A, apply_M, b, rtol=1e-8, maxiter=200, flexible=False) -> CGResult:
+def pcg(apply_A, apply_M, b, rtol=1e-8, maxiter=200, flexible=False,
+        callback=None) -> CGResult:
     """Hestenes-Stiefel PCG; ``flexible`` uses the Polak-Ribiere beta.
 
-    ``iters`` counts applications of A inside the loop.
+    ``iters`` counts applications of A inside the loop. ``callback(it, x,
+    rel)``, when given, sees every iterate and its relative residual (it
+    only observes: the iteration does not depend on it).
     """
     x = np.zeros_like(b)
     bnorm = float(np.linalg.norm(b))
@@ -57,6 +60,8 @@ def pcg(apply_A, apply_M, b, rtol=1e-8, maxiter=200, flexible=False) -> CGResult
         it += 1
         rel = float(np.linalg.norm(r)) / bnorm
         hist.append(rel)
+        if callback is not None:
+            callback(it, x, rel)
         if rel <= rtol:
             return CGResult(x, it, rel, True, hist)
         if it >= maxiter:
@@ -132,21 +137,23 @@ def mg_preconditioner(hier, params: MGParams = MGParams()):
 def mg_preconditioner_f32(hier, params: MGParams = MGParams()):
     """Float32 V-cycle used inside the float64 loop (input rounded, output widened).
 
-    Parity unpinned at the rounding level (no exact float32 target exists);
-    the tests bound its distance to the float64 V-cycle instead.
+    A whole float32 V-cycle has no bit-exact target; its parts are pinned
+    (coefficients rounded once from the exact values, the float32 column solve
+    within its forward-error bound, the one-level closed form), and the tests
+    bound its distance to the float64 V-cycle.
     """
     h32 = hier.astype(np.float32)
     return lambda r: vcycle(h32, r.astype(np.float32), params).astype(np.float64)
 
 
 def solve(hier, b, rtol=1e-8, maxiter=200, params: MGParams = MGParams(),
-          precision="fp64", flexible=False, method="cg") -> CGResult:
+          precision="fp64", flexible=False, method="cg", callback=None) -> CGResult:
     """MG-preconditioned CG (or BiCGStab, ``method="bicgstab"``) for H x = b on
     the finest level of ``hier``. With one level the preconditioner is
-    P_H^(Jac)(omega, n_coarse)."""
+    P_H^(Jac)(omega, n_coarse). ``callback`` is passed to ``pcg``."""
     M = mg_preconditioner_f32(hier, params) if precision == "fp32" else \
         mg_preconditioner(hier, params)
     A = lambda v: hier.apply(0, v)  # noqa: E731
     if method == "bicgstab":
         return bicgstab(A, M, b, rtol, maxiter)
-    return pcg(A, M, b, rtol, maxiter, flexible)
+    return pcg(A, M, b, rtol, maxiter, flexible, callback)
