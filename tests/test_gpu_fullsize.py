@@ -1,12 +1,17 @@
 """GPU parity at the benchmark's full size, C192 x 70 (15,482,880 unknowns), in
 the launch configuration the benchmark times (6 levels, 2/2 sweeps, omega 0.8,
-4 coarse sweeps). The oracle runs on the host at this size too (about 30 s)."""
+4 coarse sweeps). The oracle runs on the host at this size too: one V-cycle
+takes about 10 s on the GPU host (30 s on slower hosts), and its float64
+MG-preconditioned CG solve of the benchmark's right-hand side to 1e-12, which
+anchors the headline solves, about 2 minutes."""
+import time
+
 import numpy as np
 import pytest
 import torch
 
 import workloads
-from oracle import helmholtz, mesh, multigrid
+from oracle import helmholtz, krylov, mesh, multigrid
 
 pytestmark = pytest.mark.gpu
 
@@ -29,6 +34,65 @@ def _rel(a, ref):
     return float(np.abs(a - ref).max() / np.abs(ref).max())
 
 
+def _err(x, ref):
+    return float(np.linalg.norm(x - ref) / np.linalg.norm(ref))
+
+
+@pytest.fixture(scope="module")
+def oracle_solution(c192):
+    """The oracle's float64 MG-preconditioned CG (Section 4.1 with the V-cycle of
+    Algorithm 1) on the benchmark's right-hand side (b ~ N(0, 1), seed 1), run
+    to rtol 1e-12: its solution x_ref, the iteration at which its recursively
+    updated residual first reached 1e-6, and its iterate there."""
+    w, hier, _, _ = c192
+    b = workloads.rhs(w.N, w.nz)[0]
+    seen = {}
+    t0 = time.perf_counter()
+
+    def watch(it, x, rel):
+        print(f"  oracle CG iteration {it}: relres {rel:.3e} ({time.perf_counter() - t0:.0f} s)",
+              flush=True)
+        if rel <= 1e-6 and "it6" not in seen:
+            seen["it6"], seen["x6"] = it, x.copy()
+
+    print("oracle MG-PCG at C192x70 to rtol 1e-12", flush=True)
+    ref = krylov.solve(hier, b, rtol=1e-12, maxiter=60, callback=watch)
+    assert ref.converged
+    return b, ref.x, seen["it6"], seen["x6"]
+
+
+@pytest.mark.timeout(1200)
+def test_headline_solves_against_oracle(c192, oracle_solution):
+    """The benchmark's two solves (float32 V-cycle in float64 CG, and float64
+    throughout) to rtol 1e-6 against the oracle: iterations within +-1 of the
+    oracle's count to 1e-6; error against the oracle's 1e-12 solution within
+    1e-6 (the solution-match target), and the float64 path equal to the
+    oracle's own 1e-6 iterate to 1e-10 when it stops at the same iteration."""
+    w, hier, op64, op32 = c192
+    b, xref, it6, x6 = oracle_solution
+    bd = torch.from_numpy(b).cuda()
+    r32 = op32.solve(bd, rtol=1e-6)
+    r64 = op64.solve(bd, rtol=1e-6)
+    assert r32.converged and r64.converged
+    x32, x64 = r32.x.cpu().numpy(), r64.x.cpu().numpy()
+    e32, e64 = _err(x32, xref), _err(x64, xref)
+    o32, o64 = _err(x32, x6), _err(x64, x6)
+    t32 = np.linalg.norm(b - hier.apply(0, x32)) / np.linalg.norm(b)
+    t64 = np.linalg.norm(b - hier.apply(0, x64)) / np.linalg.norm(b)
+    print(f"oracle: {it6} iterations to 1e-6; oracle 1e-6 iterate vs x_ref {_err(x6, xref):.3e}",
+          flush=True)
+    print(f"fp32-MG: iters {r32.iters[0]}, true relres {t32:.3e}, err vs x_ref {e32:.3e}, "
+          f"vs oracle 1e-6 iterate {o32:.3e}", flush=True)
+    print(f"fp64:    iters {r64.iters[0]}, true relres {t64:.3e}, err vs x_ref {e64:.3e}, "
+          f"vs oracle 1e-6 iterate {o64:.3e}", flush=True)
+    assert abs(r32.iters[0] - it6) <= 1
+    assert abs(r64.iters[0] - it6) <= 1
+    assert e32 <= 1e-6 and e64 <= 1e-6
+    assert t32 <= 1.05e-6 and t64 <= 1.05e-6
+    if r64.iters[0] == it6:
+        assert o64 <= 1e-10
+
+
 def test_apply_full_size(c192):
     w, hier, op64, _ = c192
     x = workloads.rhs(w.N, w.nz, seed=5)[0]
@@ -37,7 +101,8 @@ def test_apply_full_size(c192):
 
 
 def test_vcycle_full_size(c192):
-    """Float64 V-cycle to 1e-10; float32 V-cycle within the float32 bound of 1e-3."""
+    """Float64 V-cycle to 1e-10; float32 V-cycle to 6e-7 (max-norm, relative:
+    about three times the 1.7e-7 measured on MI355X)."""
     w, hier, op64, op32 = c192
     print("oracle V-cycle at C192x70", flush=True)
     b = workloads.rhs(w.N, w.nz)[0]
@@ -45,8 +110,10 @@ def test_vcycle_full_size(c192):
     bd = torch.from_numpy(b).cuda()
     z64 = op64.vcycle(bd).cpu().numpy()
     z32 = op32.vcycle_f32(bd.float()).double().cpu().numpy()
+    print(f"C192x70 V-cycle: fp64 {_rel(z64, ref):.3e}, fp32 {_rel(z32, ref):.3e} "
+          "(max-norm, relative to the oracle)", flush=True)
     assert _rel(z64, ref) <= 1e-10
-    assert _rel(z32, ref) <= 1e-3
+    assert _rel(z32, ref) <= 6e-7
 
 
 def test_mixed_solve_full_size_manufactured(c192):

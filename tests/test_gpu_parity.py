@@ -92,9 +92,11 @@ def test_vcycle_parameter_variants(prm):
 def test_vcycle_fp32(N, nz, L):
     """Float32 V-cycle against the float32 emulation and the float64 V-cycle.
 
-    Bound: the smoother's column solves have condition number up to about
-    4 kv / delta = 4e3; with float32 rounding 6e-8 that gives ~2.4e-4 in the
-    worst column, so 1e-3 relative (max-norm) is the gate.
+    Gates (max-norm, relative): about three times the largest errors measured
+    on MI355X over these cases (float32 V-cycle vs the float64 oracle 2.0e-7,
+    vs the float32 emulation 5.3e-7, float64 entry point of a float32 handle
+    2.0e-7). The a-priori bound, the columns' condition number (up to about
+    4 kv / delta = 4e3) times the float32 rounding 6e-8, is 2.4e-4.
     """
     _flush(f"vcycle32 N={N} nz={nz}")
     hier, op = _setup(N, nz, L, 1.0, 1000.0, True, precision="fp32")
@@ -104,9 +106,11 @@ def test_vcycle_fp32(N, nz, L):
     torch.cuda.synchronize()
     ref64 = multigrid.vcycle(hier, b)
     ref32 = multigrid.vcycle(hier.astype(np.float32), b.astype(np.float32)).astype(np.float64)
-    assert _rel(x32.double(), ref64) <= 1e-3
-    assert _rel(x32.double(), ref32) <= 1e-3
-    assert _rel(x64in, ref64) <= 1e-3
+    _flush(f"  fp32 V-cycle vs fp64 oracle {_rel(x32.double(), ref64):.3e}, vs float32 "
+           f"emulation {_rel(x32.double(), ref32):.3e}, fp64 entry {_rel(x64in, ref64):.3e}")
+    assert _rel(x32.double(), ref64) <= 6e-7
+    assert _rel(x32.double(), ref32) <= 1.6e-6
+    assert _rel(x64in, ref64) <= 6e-7
 
 
 def test_solve_config1_fp64():
