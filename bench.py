@@ -10,19 +10,35 @@ A step is one complete solve of H x = b to relative residual 1e-6 by
 conjugate gradients in float64 preconditioned by one float32 V-cycle per
 iteration (operator apply, smoothing with column tridiagonal solves,
 residual + restriction, prolongation, coarse sweeps, float64 Krylov
-updates), with b and x resident in HBM. `value` is solves per second.
-The float64-only solve on the same seed, the V-cycle alone, the set-up, the
-adjoint (backward) step and the oracle on the host CPU are reported beside it.
+updates), with b and x resident in HBM. `value` is solves per second, timed
+with the library's kernel timing hook off. A second pass of the same steps
+with the hook on gives the dominant kernel's duration (the roofline) and the
+in-solve V-cycle time. Beside them: the float64-only solve on the same seed,
+the V-cycle entry points, the set-up, the adjoint (backward) step, the
+achievable bandwidth of plain streaming kernels, and the oracle on one host
+core (a separate single-threaded process that runs while the GPU works; its
+float64 solution to 1e-12 is what the GPU solutions' errors are measured
+against).
 """
 from __future__ import annotations
 
-import argparse
-import hashlib
-import json
 import os
-import platform
 import sys
-import time
+
+# The CPU baseline times the oracle on one host core: its worker process pins
+# the thread pools before NumPy is imported.
+_WORKER = "--cpu-baseline-worker" in sys.argv
+if _WORKER:
+    for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[_v] = "1"
+
+import argparse  # noqa: E402
+import hashlib  # noqa: E402
+import json  # noqa: E402
+import platform  # noqa: E402
+import subprocess  # noqa: E402
+import tempfile  # noqa: E402
+import time  # noqa: E402
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -35,7 +51,8 @@ PEAK_HBM_GBS = 8000.0
 
 
 def vcycle_words(L, n_pre, n_post, n_coarse):
-    """Algorithmic words per finest-level unknown of one V-cycle with these kernels.
+    """Words per finest-level unknown that one V-cycle of this library's
+    kernels moves.
 
     Per level: first sweep from zero 4 words (b, two column factors, x_new),
     further sweeps 7 (b, x, two face couplings, two factors, x_new), fused
@@ -59,6 +76,31 @@ def vcycle_words(L, n_pre, n_post, n_coarse):
         total += words * 4.0 ** (-l)
     total += smooth(n_coarse, True) * 4.0 ** (-(L - 1))
     return total
+
+
+# Words per unknown that the method itself must move, with the block-Jacobi
+# step in the residual form of Eq. jacobi (x + omega Hz^-1 (b - H x)): a sweep
+# reads b, x, the four coefficient arrays of H it needs (kh E and N, kv,
+# delta) and the column factor and writes x_new (8 words; 4 from a zero
+# guess); residual + restriction 6.25; the sweep that adds the prolongated
+# correction 8.25. This is the count the roofline and the V-cycle fraction
+# are quoted on; the kernels move fewer (see vcycle_words: the sweep is
+# evaluated in a form that needs neither delta nor kv).
+METHOD_SWEEP_WORDS = 8.0
+
+
+def method_vcycle_words(L, n_pre, n_post, n_coarse):
+    """Words per finest-level unknown of one V-cycle by the method's byte
+    model (34.5 per level above the coarsest and 28 on it for 2/2/4 sweeps)."""
+    def smooth(n):
+        return 4.0 + METHOD_SWEEP_WORDS * (n - 1) if n > 0 else 0.0
+
+    total = 0.0
+    for l in range(L - 1):
+        words = smooth(n_pre) + (6.25 if n_pre > 0 else 1.25)
+        words += (8.25 + METHOD_SWEEP_WORDS * (n_post - 1)) if n_post > 0 else 2.25
+        total += words * 4.0 ** (-l)
+    return total + smooth(n_coarse) * 4.0 ** (-(L - 1))
 
 
 def cg_bytes_per_unknown(vc_words, mixed, flexible):
@@ -118,65 +160,144 @@ def cpu_model():
     return platform.processor()
 
 
-def cpu_baseline(w, kh, kv, delta, b, iters):
-    """Time the float64 oracle on one host core on a bounded sample.
-
-    Sample: one operator apply plus one V-cycle at the full C192 x 70 size,
-    the dominant work of one preconditioned CG iteration; solves/s is
-    extrapolated with the iteration count the float64 solve needs.
-    """
-    from oracle import helmholtz, mesh, multigrid
-    t0 = time.perf_counter()
-    levels, parents, childs = mesh.hierarchy(w.N, w.nlevels)
-    hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta)
-    t1 = time.perf_counter()
-    y = hier.apply(0, b)
-    t2 = time.perf_counter()
-    z = multigrid.vcycle(hier, b)
-    t3 = time.perf_counter()
-    del y, z
-    t_iter = (t2 - t1) + (t3 - t2)
-    return {
-        "value": 1.0 / (iters * t_iter),
-        "unit": "solves/s",
-        "cores": 1,
-        "kind": "oracle",
-        "sample": (f"one float64 apply ({t2 - t1:.2f} s) + one V-cycle ({t3 - t2:.2f} s) of the "
-                   f"NumPy oracle at {w.name} on 1 host core ({cpu_model()}), scaled to "
-                   f"{iters} CG iterations per solve; oracle set-up {t1 - t0:.2f} s not counted"),
-    }
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
-def stream_reference(torch, dev, reps=10):
-    """Achievable HBM bandwidth on this GPU, as the yardstick beside the 8 TB/s
-    peak: the best of `reps` device copies (b = a) and triads (c = a + s b) of
-    1 GiB float32 arrays, run by torch's own elementwise kernels and timed with
-    events on the current stream."""
+def cpu_baseline_worker(outdir):
+    """Run in its own process (thread pools pinned to one thread before NumPy
+    was imported): the float64 oracle's set-up, one apply, one V-cycle and a
+    full MG-preconditioned CG solve at C12x10 (to 1e-8), C96x30 and C192x70
+    (to 1e-6), each timed on the wall clock. The C192x70 solve is run on to
+    1e-12; the time and iterate where its residual first reaches 1e-6 are the
+    1e-6 solve (the iteration up to there is the same), and both that iterate
+    and the 1e-12 solution are saved to `outdir` for the error of the GPU
+    solutions. Prints one JSON object."""
+    from oracle import helmholtz, krylov, mesh, multigrid
+    pools = []
+    try:
+        from threadpoolctl import threadpool_info
+        pools = [{"api": p.get("internal_api"), "threads": p.get("num_threads")}
+                 for p in threadpool_info()]
+    except Exception:  # pragma: no cover
+        pass
+    cases = []
+    for w, rtol in ((workloads.C12x10, 1e-8), (workloads.C96x30, 1e-6),
+                    (workloads.C192x70, 1e-6)):
+        kh, kv, delta = workloads.workload_coefficients(w)
+        b = workloads.rhs(w.N, w.nz)[0]
+        t0 = time.perf_counter()
+        levels, parents, childs = mesh.hierarchy(w.N, w.nlevels)
+        hier = helmholtz.Hierarchy(levels, parents, childs, kh, kv, delta)
+        t1 = time.perf_counter()
+        hier.apply(0, b)
+        t2 = time.perf_counter()
+        multigrid.vcycle(hier, b)
+        t3 = time.perf_counter()
+        _log(f"cpu baseline {w.name}: set-up {t1 - t0:.2f} s, apply {t2 - t1:.2f} s, "
+             f"V-cycle {t3 - t2:.2f} s")
+        full = w.name == "C192x70"
+        hit = {}
+
+        def watch(it, x, rel, t_start=time.perf_counter()):
+            if rel <= rtol and "t" not in hit:
+                hit.update(t=time.perf_counter() - t_start, it=it, rel=rel)
+                if full:
+                    np.save(os.path.join(outdir, "x_1e-6.npy"), x)
+            if full:
+                _log(f"  oracle CG {w.name} iteration {it}: relres {rel:.3e}")
+
+        res = krylov.solve(hier, b, rtol=1e-12 if full else rtol, maxiter=100, callback=watch)
+        if full:
+            np.save(os.path.join(outdir, "x_ref.npy"), res.x)
+        cases.append({"workload": w.name, "unknowns": w.n, "levels": w.nlevels,
+                      "setup_s": t1 - t0, "apply_s": t2 - t1, "vcycle_s": t3 - t2,
+                      "rtol": rtol, "solve_s": hit["t"], "iters": hit["it"],
+                      "relres": hit["rel"],
+                      **({"iters_to_1e-12": res.iters, "relres_final": res.relres}
+                         if full else {})})
+    print(json.dumps({"cases": cases, "cpu_count": os.cpu_count(), "cpu_model": cpu_model(),
+                      "thread_env": {v: os.environ.get(v) for v in
+                                     ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                      "MKL_NUM_THREADS")},
+                      "threadpools": pools}), flush=True)
+
+
+def start_cpu_baseline():
+    """Start the oracle worker (see cpu_baseline_worker) beside the GPU work."""
+    outdir = tempfile.mkdtemp(prefix="hh_oracle_")
+    env = dict(os.environ)
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        env[v] = "1"
+    proc = subprocess.Popen([sys.executable, os.path.abspath(__file__),
+                             "--cpu-baseline-worker", outdir],
+                            stdout=subprocess.PIPE, env=env, text=True)
+    return proc, outdir
+
+
+def finish_cpu_baseline(proc, outdir):
+    out, _ = proc.communicate()
+    if proc.returncode != 0:
+        raise RuntimeError(f"cpu baseline worker failed ({proc.returncode})")
+    rep = json.loads(out.strip().splitlines()[-1])
+    big = [c for c in rep["cases"] if c["workload"] == "C192x70"][0]
+    sample = ("measured float64 oracle solves (NumPy, one thread) on the GPU host: "
+              + "; ".join(f"{c['workload']}: {c['iters']} CG iterations to {c['rtol']:g} in "
+                          f"{c['solve_s']:.2f} s (V-cycle {c['vcycle_s']:.2f} s, apply "
+                          f"{c['apply_s']:.2f} s, set-up {c['setup_s']:.2f} s not counted)"
+                          for c in rep["cases"])
+              + "; value = 1 / the C192x70 solve time")
+    base = {"value": 1.0 / big["solve_s"], "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": sample, "cpu_model": rep["cpu_model"], "cpu_count": rep["cpu_count"],
+            "thread_env": rep["thread_env"], "threadpools": rep["threadpools"],
+            "cases": rep["cases"]}
+    x_ref = np.load(os.path.join(outdir, "x_ref.npy"))
+    x_6 = np.load(os.path.join(outdir, "x_1e-6.npy"))
+    for f in ("x_ref.npy", "x_1e-6.npy"):
+        os.remove(os.path.join(outdir, f))
+    os.rmdir(outdir)
+    return base, x_ref, x_6, big
+
+
+def stream_reference(torch, dev, lib, check, reps=10):
+    """Achievable HBM bandwidth on this GPU, the yardstick beside the 8 TB/s
+    peak: the library's own plain streaming kernels (read, write, copy and
+    triad of 1 GiB float32 arrays, 16-byte accesses), best of `reps` launches
+    each, timed with events on the stream they run on."""
     n = 1 << 28
-    a = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
-    b = torch.empty_like(a).fill_(2.0)
+    a = torch.full((n,), 1.0, dtype=torch.float32, device=dev)
+    b = torch.full((n,), 2.0, dtype=torch.float32, device=dev)
     c = torch.empty_like(a)
+    part = torch.empty(n // 4096 + 1, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev)
+    from paper_2002_00756_amd import _lib
 
-    def best(fn, nbytes):
-        fn()
+    def launch(kind):
+        dst = part if kind == _lib.BW_READ else c
+        check(lib.helmholtz_bandwidth_kernel(kind, a.data_ptr(), b.data_ptr(), dst.data_ptr(),
+                                             n, 3.0, stream.cuda_stream), "bandwidth_kernel")
+
+    def best(kind, nbytes):
+        launch(kind)
         torch.cuda.synchronize()
         ms = []
         for _ in range(reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            fn()
+            launch(kind)
             e1.record(stream)
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         return nbytes / (min(ms) * 1e-3) / 1e9
 
-    copy = best(lambda: c.copy_(a), 2 * 4 * n)
-    triad = best(lambda: torch.add(a, b, alpha=3.0, out=c), 3 * 4 * n)
-    del a, b, c
+    out = {"read_GBps": best(_lib.BW_READ, 4 * n), "write_GBps": best(_lib.BW_WRITE, 4 * n),
+           "copy_GBps": best(_lib.BW_COPY, 8 * n), "triad_GBps": best(_lib.BW_TRIAD, 12 * n)}
+    ok = bool((c == 7.0).all()) and abs(float(part.double().sum()) - n) < 1e-3 * n
+    del a, b, c, part
     torch.cuda.empty_cache()
-    return {"copy_GBps": copy, "triad_GBps": triad, "bytes": "1 GiB float32 arrays",
-            "kernels": "torch elementwise copy and add"}
+    out.update(best_GBps=max(out.values()), checked=ok,
+               kernels="helmholtz_bandwidth_kernel (hand-written HIP), 1 GiB float32 arrays")
+    return out
 
 
 def batch_leg(Operator, torch, dev, steps=2, warmup=1):
@@ -393,19 +514,28 @@ def main():
     ap.add_argument("--probe", action="store_true",
                     help="for counter runs: a few solves plus a 1 GiB device copy of known "
                          "size, no JSON")
+    ap.add_argument("--cpu-baseline-worker", metavar="OUTDIR", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_worker:
+        cpu_baseline_worker(args.cpu_baseline_worker)
+        return
     if args.gpus != 1:
         print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(it has no multi-GPU path).", file=sys.stderr)
         sys.exit(2)
+
+    w = workloads.ALL[args.workload]
+    baseline = None
+    if not args.no_cpu_baseline and not args.probe and args.workload == "C192x70":
+        baseline = start_cpu_baseline()
 
     import torch
     from paper_2002_00756_amd import Operator, _lib
     if not os.path.exists(_lib.LIB_PATH):
         from paper_2002_00756_amd import build
         build.build()
+    lib = _lib.load()
 
-    w = workloads.ALL[args.workload]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     kh, kv, delta = workloads.workload_coefficients(w)
@@ -428,13 +558,15 @@ def main():
     x = torch.empty_like(b)
     stream = torch.cuda.current_stream(dev)
 
-    def timed_solves(op, steps, warmup):
-        """Mean time of `steps` solves after `warmup` untimed ones; the
-        library's kernel timing hook covers exactly the timed solves."""
+    def timed_solves(op, steps, warmup, hook=False):
+        """Mean time of `steps` solves after `warmup` untimed ones, bracketed by
+        device synchronisations. With `hook` the library's kernel timing hook
+        records the timed solves' profiled launches."""
         for _ in range(warmup):
             op.solve(b, rtol=args.rtol, out=x)
         torch.cuda.synchronize()
-        op.profile(True)
+        if hook:
+            op.profile(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         its = []
         e0.record(stream)
@@ -458,28 +590,34 @@ def main():
         print("probe done", flush=True)
         return
 
-    # --- the metric: mixed-precision solves -------------------------------
+    # --- the metric: mixed-precision solves, timing hook off ----------------
     ms32, wall32, its32, res32 = timed_solves(op32, args.steps, args.warmup)
-    sweep_ms, sweep_n, sweep_bytes = op32.profile_read(_lib.PROF_SWEEP_FINE)
-    op32.profile(False)
     x32 = x.clone()
     true32 = float(torch.linalg.norm(b - op64.apply(x32)) / torch.linalg.norm(b))
-
-    # --- float64-only path on the same seed ---------------------------------
+    # --- float64-only path on the same seed ----------------------------------
     ms64, wall64, its64, res64 = timed_solves(op64, args.steps, args.warmup)
-    sw64_ms, sw64_n, sw64_bytes = op64.profile_read(_lib.PROF_SWEEP_FINE)
-    ap_ms, ap_n, ap_bytes = op64.profile_read(_lib.PROF_APPLY_FINE)
-    op64.profile(False)
     x64 = x.clone()
     true64 = float(torch.linalg.norm(b - op64.apply(x64)) / torch.linalg.norm(b))
-    # reference solution: float64 solve to 1e-12
-    xref = op64.solve(b, rtol=1e-12).x
-    err32 = float(torch.linalg.norm(x32 - xref) / torch.linalg.norm(xref))
-    err64 = float(torch.linalg.norm(x64 - xref) / torch.linalg.norm(xref))
 
-    # --- V-cycle alone --------------------------------------------------------
-    words = vcycle_words(w.nlevels, prm["n_pre"], prm["n_post"], prm["n_coarse"])
+    # --- the same steps again with the kernel timing hook on -----------------
+    # (dominant kernel, float64 apply and the whole in-solve V-cycle)
+    hms32, _, _, _ = timed_solves(op32, args.steps, 2, hook=True)
+    sweep_ms, sweep_n, sweep_kbytes = op32.profile_read(_lib.PROF_SWEEP_FINE)
+    vc32_ms, vc32_n, vc32_kbytes = op32.profile_read(_lib.PROF_VCYCLE)
+    op32.profile(False)
+    hms64, _, _, _ = timed_solves(op64, args.steps, 2, hook=True)
+    sw64_ms, sw64_n, sw64_kbytes = op64.profile_read(_lib.PROF_SWEEP_FINE)
+    ap_ms, ap_n, ap_bytes = op64.profile_read(_lib.PROF_APPLY_FINE)
+    vc64_ms_in, vc64_n, vc64_kbytes = op64.profile_read(_lib.PROF_VCYCLE)
+    op64.profile(False)
+
+    # reference solution on the GPU (float64 to 1e-12), used when the oracle's is absent
+    xref_gpu = op64.solve(b, rtol=1e-12).x
+
+    # --- V-cycle entry points (ABI layout in and out) ------------------------
     n = w.n
+    words = vcycle_words(w.nlevels, prm["n_pre"], prm["n_post"], prm["n_coarse"])
+    mwords = method_vcycle_words(w.nlevels, prm["n_pre"], prm["n_post"], prm["n_coarse"])
 
     def time_vcycle(fn, arg, reps=20):
         for _ in range(3):
@@ -494,13 +632,9 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     b32 = b.float()
-    vc32_ms = time_vcycle(op32.vcycle_f32, b32)
-    vc64_ms = time_vcycle(op64.vcycle, b)
-    # the entry points take b and return z in the ABI layout: one read and one
-    # write each way to and from the tiled layout (4 words) besides the V-cycle
-    conv_words = 4.0
-    vc32_gbs = (words + conv_words) * 4 * n / (vc32_ms * 1e-3) / 1e9
-    vc64_gbs = (words + conv_words) * 8 * n / (vc64_ms * 1e-3) / 1e9
+    vce32_ms = time_vcycle(op32.vcycle_f32, b32)
+    vce64_ms = time_vcycle(op64.vcycle, b)
+    conv_words = 4.0   # the entry points convert b and x between the ABI and tiled layouts
 
     # --- adjoint step: forward solve + adjoint solve + face gradients ---------
     g = torch.from_numpy(workloads.loss_weights(w.N, w.nz)[0]).to(dev)
@@ -514,13 +648,21 @@ def main():
     torch.cuda.synchronize()
     adj_ms = (time.perf_counter() - t) / reps_adj * 1e3
 
-    ref = stream_reference(torch, dev)
-    stream_gbs = max(ref["copy_GBps"], ref["triad_GBps"])
+    ref = stream_reference(torch, dev, lib, _lib.check)
+    stream_gbs = ref["best_GBps"]
 
     # --- dominant kernel: fine-level float32 smoothing sweep -----------------
     sweep_avg_ms = sweep_ms / max(sweep_n, 1)
-    achieved = (sweep_bytes / max(sweep_n, 1)) / (sweep_avg_ms * 1e-3) / 1e9
+    sweep_method_bytes = METHOD_SWEEP_WORDS * 4 * n
+    achieved = sweep_method_bytes / (sweep_avg_ms * 1e-3) / 1e9
     traffic = measured_traffic(os.path.join(ROOT, "profiles", "traffic_sweep_f32_C192x70.txt"))
+
+    def vc_stats(ms, cnt, kbytes, word):
+        avg = ms / max(cnt, 1)
+        return {"ms": avg, "count": cnt,
+                "GBps": mwords * word * n / (avg * 1e-3) / 1e9,
+                "frac": mwords * word * n / (avg * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                "GBps_kernel_words": kbytes / max(cnt, 1) / (avg * 1e-3) / 1e9}
 
     per_iter32 = cg_bytes_per_unknown(words, True, args.cg == "flexible")
     per_iter64 = cg_bytes_per_unknown(words, False, False)
@@ -554,40 +696,61 @@ def main():
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
+            "algorithmic_bytes_per_launch": sweep_method_bytes,
+            "words_per_unknown": METHOD_SWEEP_WORDS,
+            "kernel_words_per_unknown": 7.0,
+            "achieved_kernel_words": sweep_kbytes / max(sweep_n, 1) / (sweep_avg_ms * 1e-3) / 1e9,
             "frac_of_stream": achieved / stream_gbs,
             "avg_launch_us": sweep_avg_ms * 1e3,
             "launches": sweep_n,
-            "algorithmic_bytes_per_launch": sweep_bytes / max(sweep_n, 1),
+            "timed_in": "second pass of the timed solves with the library's event hook on",
         },
         "fp32_mg": {
             "solves_per_s": 1e3 / ms32, "ms_per_solve": ms32, "host_wall_ms": wall32,
-            "iters": it32, "true_relres": true32, "err_vs_fp64_1e-12": err32,
+            "ms_per_solve_hook_on": hms32,
+            "iters": it32, "true_relres": true32,
             "cg_GBps": it32 * per_iter32 * n / (ms32 * 1e-3) / 1e9,
         },
         "fp64_mg": {
             "solves_per_s": 1e3 / ms64, "ms_per_solve": ms64, "host_wall_ms": wall64,
-            "iters": it64, "true_relres": true64, "err_vs_fp64_1e-12": err64,
+            "ms_per_solve_hook_on": hms64,
+            "iters": it64, "true_relres": true64,
             "cg_GBps": it64 * per_iter64 * n / (ms64 * 1e-3) / 1e9,
-            "sweep_fine_GBps": (sw64_bytes / max(sw64_n, 1)) / (sw64_ms / max(sw64_n, 1) * 1e-3)
+            "sweep_fine_GBps": METHOD_SWEEP_WORDS * 8 * n / (sw64_ms / max(sw64_n, 1) * 1e-3)
             / 1e9 if sw64_n else None,
             "apply_fine_GBps": (ap_bytes / max(ap_n, 1)) / (ap_ms / max(ap_n, 1) * 1e-3) / 1e9
             if ap_n else None,
         },
         "speedup_fp32mg_vs_fp64": ms64 / ms32,
-        "vcycle": {
-            "words_per_unknown": words, "entry_conversion_words": conv_words,
-            "fp32_ms": vc32_ms, "fp32_GBps": vc32_gbs, "fp32_frac": vc32_gbs / PEAK_HBM_GBS,
-            "fp64_ms": vc64_ms, "fp64_GBps": vc64_gbs, "fp64_frac": vc64_gbs / PEAK_HBM_GBS,
-            "fp32_frac_of_stream": vc32_gbs / stream_gbs,
-            "fp64_frac_of_stream": vc64_gbs / stream_gbs,
+        "vcycle_in_solve": {
+            "words_per_unknown": mwords, "kernel_words_per_unknown": words,
+            "fp32": vc_stats(vc32_ms, vc32_n, vc32_kbytes, 4),
+            "fp64": vc_stats(vc64_ms_in, vc64_n, vc64_kbytes, 8),
+            "note": "device time of each whole V-cycle inside the timed solves (event pair "
+                    "around all its launches, gaps included)",
+        },
+        "vcycle_entry_points": {
+            "fp32_ms": vce32_ms, "fp64_ms": vce64_ms,
+            "fp32_GBps": (mwords + conv_words) * 4 * n / (vce32_ms * 1e-3) / 1e9,
+            "fp64_GBps": (mwords + conv_words) * 8 * n / (vce64_ms * 1e-3) / 1e9,
+            "note": "helmholtz_vcycle_f32 / helmholtz_vcycle, which also convert b and x "
+                    "between the ABI and tiled layouts (4 more words per unknown)",
         },
         "stream_reference": ref,
         "setup_ms": setup_ms,
         "adjoint_step_ms": adj_ms,
     }
+    out["vcycle_in_solve"]["fp32"]["frac_of_stream"] = \
+        out["vcycle_in_solve"]["fp32"]["GBps"] / stream_gbs
+    x64_np = x64.cpu().numpy()
+    x32_np = x32.cpu().numpy()
+    xg = xref_gpu.cpu().numpy()
+    err = lambda a, r: float(np.linalg.norm(a - r) / np.linalg.norm(r))  # noqa: E731
+    out["fp32_mg"]["err_vs_gpu_fp64_1e-12"] = err(x32_np, xg)
+    out["fp64_mg"]["err_vs_gpu_fp64_1e-12"] = err(x64_np, xg)
+    del op32, op64, kh_d, kv_d, dl_d, xref_gpu
+    torch.cuda.empty_cache()
     if not args.no_batch_leg and args.workload == "C192x70":
-        del op32, op64, kh_d, kv_d, dl_d
-        torch.cuda.empty_cache()
         out["batch4_C384x70"] = batch_leg(Operator, torch, dev)
     if not args.no_solver_comparison and args.workload == "C192x70":
         out["solver_comparison"] = solver_comparison(Operator, torch, dev)
@@ -595,8 +758,15 @@ def main():
         out["nine_cell_C192x70"] = nine_cell_leg(Operator, torch, dev, _lib)
     if not args.no_weighted and args.workload == "C192x70":
         out["nonsymmetric_C192x70"] = weighted_leg(Operator, torch, dev)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, kh, kv, delta, b_np, int(round(it64)))
+    if baseline is not None:
+        base, x_ref, x_6, big = finish_cpu_baseline(*baseline)
+        out["cpu_baseline"] = base
+        for key, xs in (("fp32_mg", x32_np), ("fp64_mg", x64_np)):
+            out[key]["err_vs_oracle_1e-12"] = err(xs, x_ref)
+            out[key]["err_vs_oracle_1e-6_iterate"] = err(xs, x_6)
+        out["oracle_C192x70"] = {"iters_to_1e-6": big["iters"],
+                                 "iters_to_1e-12": big["iters_to_1e-12"],
+                                 "err_1e-6_iterate_vs_1e-12": err(x_6, x_ref)}
     print(json.dumps(out), flush=True)
 
 

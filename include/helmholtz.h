@@ -151,6 +151,16 @@ int helmholtz_create_weighted(const helmholtz_config* cfg, const double* kh, con
                               size_t workspace_bytes, helmholtz_stream_t stream,
                               helmholtz_t* out);
 
+/* Replace the operator of an existing handle: the coefficient part of
+ * set-up only (coarse levels by re-discretisation, column factors, float32
+ * copies); the mesh tables and the workspace stay. Arguments as for the
+ * create call that made the handle: kv2 non-NULL exactly for a 9-cell handle
+ * with nz > 2, s exactly for a weighted one. Validation as at create; on an
+ * error the handle holds no usable operator until an update succeeds.
+ * Synchronises `stream` once. */
+int helmholtz_update(helmholtz_t h, const double* kh, const double* kv, const double* kv2,
+                     const double* delta, const double* s, helmholtz_stream_t stream);
+
 /* Release host state (handle, pinned scalars). Never touches the workspace. */
 int helmholtz_destroy(helmholtz_t h);
 
@@ -276,11 +286,36 @@ int helmholtz_mesh_tables(int32_t N, int32_t* nbr, int32_t* ftab, int32_t* paren
  *                               and the two column factors, writes x_new:
  *                               7 words per unknown)
  *   HELMHOLTZ_PROF_APPLY_FINE   float64 operator apply on the finest level
- *                               (reads x, kh[2], kv, delta, writes y: 6 words) */
-enum { HELMHOLTZ_PROF_SWEEP_FINE = 0, HELMHOLTZ_PROF_APPLY_FINE = 1, HELMHOLTZ_PROF_COUNT = 2 };
+ *                               (reads x, kh[2], kv, delta, writes y: 6 words)
+ *   HELMHOLTZ_PROF_VCYCLE       each whole V-cycle inside helmholtz_solve (one
+ *                               event pair around all its launches, gaps
+ *                               between them included); bytes: the words its
+ *                               kernels must move on every level (first sweep
+ *                               from zero 4, further sweeps 7, residual +
+ *                               restriction 6.25, sweep with prolongation
+ *                               7.25; one more per sweep and residual for the
+ *                               9-cell and the row-weighted operator), times
+ *                               the unknowns of the level and the batch */
+enum { HELMHOLTZ_PROF_SWEEP_FINE = 0, HELMHOLTZ_PROF_APPLY_FINE = 1, HELMHOLTZ_PROF_VCYCLE = 2,
+       HELMHOLTZ_PROF_COUNT = 3 };
 int helmholtz_profile_enable(helmholtz_t h, int enable);
 int helmholtz_profile_read(helmholtz_t h, int32_t kernel, double* ms /* host */,
                            int64_t* launches /* host */, double* bytes /* host */);
+
+/* Achievable-bandwidth yardstick (instrumentation, not part of the method):
+ * one launch of a plain streaming kernel over n float32 values, 16-byte
+ * vector accesses, one pass:
+ *   HELMHOLTZ_BW_READ   reads a; writes one partial sum per 4096 values to c
+ *                       (so c needs n / 4096 floats rounded up)
+ *   HELMHOLTZ_BW_WRITE  c = s
+ *   HELMHOLTZ_BW_COPY   c = a
+ *   HELMHOLTZ_BW_TRIAD  c = a + s b
+ * a, b, c device arrays (unused ones may be NULL), 16-byte aligned, n a
+ * multiple of 4, n / 4096 < 2^31. Asynchronous. */
+enum { HELMHOLTZ_BW_READ = 0, HELMHOLTZ_BW_WRITE = 1, HELMHOLTZ_BW_COPY = 2,
+       HELMHOLTZ_BW_TRIAD = 3 };
+int helmholtz_bandwidth_kernel(int32_t kind, const float* a, const float* b, float* c, int64_t n,
+                               float s, helmholtz_stream_t stream);
 
 /* Static description of a return code. */
 const char* helmholtz_strerror(int code);

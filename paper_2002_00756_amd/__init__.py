@@ -10,4 +10,4 @@ The computation lives in the HIP library ``libhelmholtz.so`` (C ABI in
 """
 from ._lib import HelmholtzError, load  # noqa: F401
 from .solver import Operator, SolveResult, mesh_tables  # noqa: F401
-from .autograd import HelmholtzSolve, helmholtz_solve  # noqa: F401
+from .autograd import HelmholtzNotConverged, HelmholtzSolve, helmholtz_solve  # noqa: F401

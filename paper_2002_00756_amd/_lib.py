@@ -44,6 +44,7 @@ SIGNATURES = {
     "helmholtz_create_weighted": (_c_int, [ctypes.POINTER(Config), _dp, _dp, _dp, _dp, _vp,
                                            _c_size, _vp, ctypes.POINTER(_vp)]),
     "helmholtz_destroy": (_c_int, [_vp]),
+    "helmholtz_update": (_c_int, [_vp, _dp, _dp, _dp, _dp, _dp, _vp]),
     "helmholtz_apply_adjoint": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_vcycle_adjoint": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _vp]),
     "helmholtz_face_grad_weighted": (_c_int, [_vp, _dp, _dp, ctypes.c_int32, _dp, _dp, _dp, _dp,
@@ -63,8 +64,11 @@ SIGNATURES = {
     "helmholtz_profile_enable": (_c_int, [_vp, _c_int]),
     "helmholtz_profile_read": (_c_int, [_vp, ctypes.c_int32, _f64p,
                                         ctypes.POINTER(ctypes.c_int64), _f64p]),
+    "helmholtz_bandwidth_kernel": (_c_int, [ctypes.c_int32, _vp, _vp, _vp, ctypes.c_int64,
+                                            ctypes.c_float, _vp]),
 }
-PROF_SWEEP_FINE, PROF_APPLY_FINE = 0, 1
+PROF_SWEEP_FINE, PROF_APPLY_FINE, PROF_VCYCLE = 0, 1, 2
+BW_READ, BW_WRITE, BW_COPY, BW_TRIAD = 0, 1, 2, 3
 
 _lib = None
 

@@ -662,17 +662,47 @@ void retile(const helmholtz_s* h, const S* src, D* dst, int batch, hipStream_t s
                        s, src, dst, v.ncol, h->nz, v.nvp);
 }
 
+// Algorithmic bytes of one V-cycle with these kernels (the words each kernel
+// must move per unknown of its level, times the unknowns and the batch):
+// first sweep from zero 4 words (b, two factors, x_new), further sweeps 7
+// (b, x, two face couplings, two factors, x_new), residual + restriction 6.25
+// (b, x, kh[2], kv, delta; a quarter-size coarse b), sweep with prolongation
+// 7.25 (the coarse x), a lone prolongation 2.25; the 9-cell and the weighted
+// operators add one word (kv2 or s) to every sweep and residual.
+double vcycle_bytes(const helmholtz_s* h, int batch, size_t word) {
+    const helmholtz_config& c = h->cfg;
+    const double extra = (h->nine || h->weighted) ? 1.0 : 0.0;
+    const double sw = 7.0 + extra;
+    auto smooth = [&](int n) { return n > 0 ? 4.0 + sw * (n - 1) : 0.0; };
+    double total = 0.0;
+    for (int l = 0; l < h->L; ++l) {
+        double w;
+        if (l == h->L - 1) {
+            w = smooth(c.n_coarse);
+        } else {
+            w = smooth(c.n_pre) + (c.n_pre > 0 ? 6.25 + extra : 1.25);
+            w += c.n_post > 0 ? sw + 0.25 + sw * (c.n_post - 1) : 2.25;
+        }
+        total += w * double(h->nz) * h->lev[l].ncol;
+    }
+    return total * double(batch) * double(word);
+}
+
 // z = M r on the finest level in the handle's precision (tiled vectors). The
 // float32 V-cycle reads r32 (the level-0 float32 right-hand side, which the
 // Krylov kernels keep equal to float(r)) and leaves z32 in the level-0 float32
-// solution buffer; r and z are then not touched.
+// solution buffer; r and z are then not touched. `prof`: time the V-cycle
+// with the kernel timing hook (the solves).
 int precondition(helmholtz_s* h, const double* r, double* z, int batch, const int* active,
-                 hipStream_t s) {
-    if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
+                 hipStream_t s, bool prof = false) {
+    const bool mixed = h->cfg.mg_precision == HELMHOLTZ_FP32;
+    prof = prof && prof_begin(h, HELMHOLTZ_PROF_VCYCLE, s);
+    if (!mixed) {
         vcycle_level<double>(h, h->vb64, 0, r, z, batch, active, s);
     } else {
         vcycle_level<float>(h, h->vb32, 0, h->vb32.b[0], h->vb32.x[0], batch, active, s);
     }
+    if (prof) prof_end(h, HELMHOLTZ_PROF_VCYCLE, vcycle_bytes(h, batch, mixed ? 4 : 8), s);
     return last_error();
 }
 
@@ -710,13 +740,18 @@ int wait_published(helmholtz_s* h, hipStream_t s, const std::vector<int>& need, 
 // and out through the level-0 float32 buffers).
 int precondition_into(helmholtz_s* h, const double* u, double* out, int batch, const int* active,
                       hipStream_t s) {
-    if (h->cfg.mg_precision == HELMHOLTZ_FP64) {
+    const bool mixed = h->cfg.mg_precision == HELMHOLTZ_FP32;
+    if (!mixed) {
+        const bool prof = prof_begin(h, HELMHOLTZ_PROF_VCYCLE, s);
         vcycle_level<double>(h, h->vb64, 0, u, out, batch, active, s);
+        if (prof) prof_end(h, HELMHOLTZ_PROF_VCYCLE, vcycle_bytes(h, batch, 8), s);
     } else {
         const VBufs<float>& V = h->vb32;
         const int64_t n = int64_t(batch) * h->nvp;
         convert<double, float>(u, V.b[0], n, s);
+        const bool prof = prof_begin(h, HELMHOLTZ_PROF_VCYCLE, s);
         vcycle_level<float>(h, V, 0, V.b[0], V.x[0], batch, active, s);
+        if (prof) prof_end(h, HELMHOLTZ_PROF_VCYCLE, vcycle_bytes(h, batch, 4), s);
         convert<float, double>(V.x[0], out, n, s);
     }
     return last_error();
@@ -785,6 +820,8 @@ int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
 int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
                 const double* kv2, const double* delta, const double* sw, void* workspace,
                 size_t workspace_bytes, helmholtz_stream_t stream_, helmholtz_t* out);
+int set_coefficients(helmholtz_s* h, const double* kh, const double* kv, const double* kv2,
+                     const double* delta, const double* sw, hipStream_t s);
 
 // Level vectors b, x, t of every level for `batch` right-hand sides, carved
 // from `base`; returns the bytes they take.
@@ -978,8 +1015,18 @@ int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
         if (hipStreamSynchronize(s) != hipSuccess) return fail(HELMHOLTZ_EHIP);
     }
 
-    // coefficients: finest level from the caller, coarser by re-discretisation
-    if (hipMemsetAsync(h->flags, 0, 4 * sizeof(int), s) != hipSuccess) return fail(HELMHOLTZ_EHIP);
+    if (int e = set_coefficients(h, kh, kv, kv2, delta, sw, s)) return fail(e);
+    *out = h;
+    return HELMHOLTZ_OK;
+}
+
+// Coefficients of every level: finest from the caller (validated), coarser by
+// re-discretisation, then the column factors and the float32 copies.
+// Synchronises `s` once.
+int set_coefficients(helmholtz_s* h, const double* kh, const double* kv, const double* kv2,
+                     const double* delta, const double* sw, hipStream_t s) {
+    const int nz = h->nz;
+    if (hipMemsetAsync(h->flags, 0, 4 * sizeof(int), s) != hipSuccess) return HELMHOLTZ_EHIP;
     {
         Level& v = h->lev[0];
         const int64_t nv = int64_t(nz) * v.ncol;
@@ -1009,19 +1056,26 @@ int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
         if (h->nine) convert<double, float>(v.d.kv2, v.f.kv2, nv, s);
         if (h->weighted) convert<double, float>(v.d.s, v.f.s, nv, s);
     }
-    if (last_error() != HELMHOLTZ_OK) return fail(HELMHOLTZ_EHIP);
+    if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
     if (hipMemcpyAsync(h->hflags, h->flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess)
-        return fail(HELMHOLTZ_EHIP);
-    if (hipStreamSynchronize(s) != hipSuccess) return fail(HELMHOLTZ_EHIP);
-    if (h->hflags[0] & 1) return fail(HELMHOLTZ_ENONFINITE);
-    if (h->hflags[0] & 2) return fail(HELMHOLTZ_EINVAL);
-    *out = h;
+        return HELMHOLTZ_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return HELMHOLTZ_EHIP;
+    if (h->hflags[0] & 1) return HELMHOLTZ_ENONFINITE;
+    if (h->hflags[0] & 2) return HELMHOLTZ_EINVAL;
     return HELMHOLTZ_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+int helmholtz_update(helmholtz_t h, const double* kh, const double* kv, const double* kv2,
+                     const double* delta, const double* s, helmholtz_stream_t stream) {
+    if (!h || !kh || !delta || (h->nz > 1 && !kv)) return HELMHOLTZ_EINVAL;
+    if ((kv2 != nullptr) != (h->nine && h->nz > 2)) return HELMHOLTZ_EINVAL;
+    if ((s != nullptr) != h->weighted) return HELMHOLTZ_EINVAL;
+    return set_coefficients(h, kh, kv, kv2, delta, s, reinterpret_cast<hipStream_t>(stream));
+}
 
 int helmholtz_profile_enable(helmholtz_t h, int enable) {
     if (!h) return HELMHOLTZ_EINVAL;
@@ -1181,7 +1235,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     };
 
     // z = M r, rho = r.z, p = z
-    if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
+    if (int e = precondition(h, h->r, h->z, batch, h->active, s, true)) return e;
     dot_rz(nullptr);
     hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRho), kRedBlocks, 0);
     p_update(1, kXNone);
@@ -1235,7 +1289,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         }
         if (some_done) x_update(xmode, 1);
         // z = M r, beta, p = z + beta p (with the owed x update)
-        if (int e = precondition(h, h->r, h->z, batch, h->active, s)) return e;
+        if (int e = precondition(h, h->r, h->z, batch, h->active, s, true)) return e;
         dot_rz(flex ? h->q : nullptr);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st,
                            int(flex ? kFinBetaFlex : kFinBeta), kRedBlocks, 0);
@@ -1244,6 +1298,41 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     // the caller may read x as soon as this returns on the host
     HH_CHECK(hipStreamSynchronize(s));
     return finish(status);
+}
+
+int helmholtz_bandwidth_kernel(int32_t kind, const float* a, const float* b, float* c, int64_t n,
+                               float sv, helmholtz_stream_t stream) {
+    if (n <= 0 || n % 4 != 0) return HELMHOLTZ_EINVAL;
+    const int64_t nblk = (n + kStreamPerBlock - 1) / kStreamPerBlock;
+    if (nblk >= (int64_t(1) << 31)) return HELMHOLTZ_ESHAPE;
+    auto aligned = [](const void* p) { return reinterpret_cast<uintptr_t>(p) % 16 == 0; };
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const float4* a4 = reinterpret_cast<const float4*>(a);
+    const float4* b4 = reinterpret_cast<const float4*>(b);
+    float4* c4 = reinterpret_cast<float4*>(c);
+    const int64_t n4 = n / 4;
+    const dim3 grid(static_cast<unsigned>(nblk)), blk(kBlock);
+    switch (kind) {
+        case HELMHOLTZ_BW_READ:
+            if (!a || !c || !aligned(a)) return HELMHOLTZ_EINVAL;
+            hipLaunchKernelGGL(k_stream<kStreamRead>, grid, blk, 0, s, a4, b4, c4, n4, sv, c);
+            break;
+        case HELMHOLTZ_BW_WRITE:
+            if (!c || !aligned(c)) return HELMHOLTZ_EINVAL;
+            hipLaunchKernelGGL(k_stream<kStreamWrite>, grid, blk, 0, s, a4, b4, c4, n4, sv, c);
+            break;
+        case HELMHOLTZ_BW_COPY:
+            if (!a || !c || !aligned(a) || !aligned(c)) return HELMHOLTZ_EINVAL;
+            hipLaunchKernelGGL(k_stream<kStreamCopy>, grid, blk, 0, s, a4, b4, c4, n4, sv, c);
+            break;
+        case HELMHOLTZ_BW_TRIAD:
+            if (!a || !b || !c || !aligned(a) || !aligned(b) || !aligned(c)) return HELMHOLTZ_EINVAL;
+            hipLaunchKernelGGL(k_stream<kStreamTriad>, grid, blk, 0, s, a4, b4, c4, n4, sv, c);
+            break;
+        default:
+            return HELMHOLTZ_EINVAL;
+    }
+    return last_error();
 }
 
 int helmholtz_face_grad(helmholtz_t h, const double* lam, const double* x, int32_t batch,

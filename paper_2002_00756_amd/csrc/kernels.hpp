@@ -1469,4 +1469,46 @@ k_face_grad(int ncol, int nz, const int32_t* __restrict__ nbr, const double* __r
     gdl[i] = gd;
 }
 
+// ---------------------------------------------------------------------------
+// Achievable-bandwidth yardstick: one pass of a plain streaming kernel,
+// 16-byte accesses, each thread four vectors 256 apart (all loads of a thread
+// issued before its stores). Not part of the method.
+enum { kStreamRead = 0, kStreamWrite = 1, kStreamCopy = 2, kStreamTriad = 3 };
+constexpr int kStreamUnroll = 4;
+constexpr int64_t kStreamPerBlock = int64_t(kBlock) * kStreamUnroll * 4;  // floats per block
+
+template <int KIND>
+__global__ void __launch_bounds__(kBlock)
+k_stream(const float4* __restrict__ a, const float4* __restrict__ b, float4* __restrict__ c,
+         int64_t n4, float s, float* __restrict__ partial) {
+    __shared__ double sh[kBlock / 64];
+    const int64_t i0 = int64_t(blockIdx.x) * (kBlock * kStreamUnroll) + threadIdx.x;
+    float4 va[kStreamUnroll], vb[kStreamUnroll];
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t i = i0 + int64_t(u) * kBlock;
+        if (i < n4) {
+            if (KIND != kStreamWrite) va[u] = a[i];
+            if (KIND == kStreamTriad) vb[u] = b[i];
+        }
+    }
+    float acc = 0.f;
+#pragma unroll
+    for (int u = 0; u < kStreamUnroll; ++u) {
+        const int64_t i = i0 + int64_t(u) * kBlock;
+        if (i < n4) {
+            if (KIND == kStreamRead) acc += (va[u].x + va[u].y) + (va[u].z + va[u].w);
+            if (KIND == kStreamWrite) c[i] = make_float4(s, s, s, s);
+            if (KIND == kStreamCopy) c[i] = va[u];
+            if (KIND == kStreamTriad)
+                c[i] = make_float4(va[u].x + s * vb[u].x, va[u].y + s * vb[u].y,
+                                   va[u].z + s * vb[u].z, va[u].w + s * vb[u].w);
+        }
+    }
+    if (KIND == kStreamRead) {
+        const double t = block_sum(double(acc), sh);
+        if (threadIdx.x == 0) partial[blockIdx.x] = float(t);
+    }
+}
+
 }  // namespace hh

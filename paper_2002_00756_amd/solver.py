@@ -126,6 +126,23 @@ class Operator:
         _lib.check(code, "helmholtz_create")
         self._h = handle
 
+    def update(self, kh, kv, delta, kv2=None, s=None):
+        """Replace the operator's coefficients (same mesh, levels and options):
+        the coefficient part of set-up only. ``kv2`` / ``s`` as at construction."""
+        kh = _dev(kh, torch.float64, self.device, (2, self.nz, self.ncol))
+        delta = _dev(delta, torch.float64, self.device, (self.nz, self.ncol))
+        kv = _dev(kv, torch.float64, self.device, (self.nz - 1, self.ncol)) if self.nz > 1 else None
+        if (kv2 is not None) != self.nine or (s is not None) != self.weighted:
+            raise ValueError("update must pass kv2 / s exactly as the operator was built")
+        kv2 = _dev(kv2, torch.float64, self.device, (self.nz - 2, self.ncol)) \
+            if self.nine and self.nz > 2 else None
+        s = _dev(s, torch.float64, self.device, (self.nz, self.ncol)) if self.weighted else None
+        ptr = lambda t: t.data_ptr() if t is not None else None  # noqa: E731
+        with torch.cuda.device(self.device):
+            code = self.lib.helmholtz_update(self._h, kh.data_ptr(), ptr(kv), ptr(kv2),
+                                             delta.data_ptr(), ptr(s), _stream_ptr(self.device))
+        _lib.check(code, "helmholtz_update")
+
     def close(self):
         if getattr(self, "_h", None):
             self.lib.helmholtz_destroy(self._h)
