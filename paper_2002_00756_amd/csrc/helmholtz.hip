@@ -60,6 +60,7 @@ struct Level {
     int32_t* nbr = nullptr;     // [4][ncol]
     uint32_t* fface = nullptr;  // [2][ncol] offsets of the W and S faces in kh
     int32_t* parent = nullptr;  // [ncol] into level + 1 (not on the coarsest)
+    int32_t* pofs = nullptr;    // [3][ncol] prolongation offsets (not on the coarsest)
     int32_t* child = nullptr;   // [4][ncol] into level - 1 (not on the finest)
     LevelData<double> d;
     LevelData<float> f;
@@ -195,6 +196,14 @@ struct helmholtz_s {
     // point) and the device the handle was created on
     unsigned char* scratch = nullptr;
     int device = -1;
+    // traversal direction of the next kernel on each level (alternates, see
+    // xcd_remap)
+    mutable int dir[kMaxLevels] = {};
+    int flip(int l) const {
+        const int d = dir[l];
+        dir[l] ^= 1;
+        return d;
+    }
 };
 
 namespace {
@@ -208,6 +217,7 @@ void layout(helmholtz_s* h, Carver& cv) {
         v.nbr = cv.take<int32_t>(4 * nc);
         v.fface = cv.take<uint32_t>(2 * nc);
         v.parent = (l + 1 < h->L) ? cv.take<int32_t>(nc) : nullptr;
+        v.pofs = (l + 1 < h->L) ? cv.take<int32_t>(3 * nc) : nullptr;
         v.child = (l > 0) ? cv.take<int32_t>(4 * nc) : nullptr;
         v.d.kh = cv.take<double>(2 * nv);
         v.d.kv = cv.take<double>(nv);
@@ -351,14 +361,8 @@ LevelView<T> view(const helmholtz_s* h, int l) {
         if constexpr (std::is_same<T, double>::value) return v.d;
         else return v.f;
     }();
-    return LevelView<T>{v.ncol, h->nz, v.nvp, v.nbr, v.fface, d.kh, d.kv, d.dl, d.cc, d.mm,
-                        d.kv2, d.s};
-}
-
-template <typename T>
-const VBufs<T>& ws_bufs(const helmholtz_s* h) {
-    if constexpr (std::is_same<T, double>::value) return h->vb64;
-    else return h->vb32;
+    return LevelView<T>{v.ncol, h->nz, v.nvp, v.N,  v.nbr, v.fface, v.pofs,
+                        d.kh,   d.kv,  d.dl,  d.cc, d.mm,  d.kv2,  d.s};
 }
 
 // ---- sweep launch: compile-time bound on levels per thread ---------------
@@ -380,13 +384,13 @@ void launch_sweep_b(const helmholtz_s* h, int l, const T* b, const T* x, const T
     const Level& v = h->lev[l];
     using Tile = SweepTile<T, TC, kBlock>;
     const int ntile = (v.ncol + TC - 1) / TC;
-    const int32_t* par = (l + 1 < h->L) ? v.parent : nullptr;
     const int nvp_c = (l + 1 < h->L) ? h->lev[l + 1].nvp : 0;
     const bool prof = (l == 0 && MODE == kPlain) && prof_begin(h, HELMHOLTZ_PROF_SWEEP_FINE, s);
+    const int rev = h->flip(l);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, dim3(ntile * batch), dim3(kBlock), Tile::lds_bytes(h->nz), s,
-                           view<T>(h, l), b, x, xc, par, nvp_c, y, T(h->cfg.omega), batch, active,
-                           sweep_mid(h->nz));
+                           view<T>(h, l), b, x, xc, nvp_c, y, T(h->cfg.omega), batch, active,
+                           sweep_mid(h->nz), rev);
     };
     // only the large levels use 32-column tiles and can stream past the cache
     constexpr bool kCanStream = TC == kTile;
@@ -490,9 +494,10 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
     const uintptr_t al = 2 * sizeof(T);
     const bool pair = reinterpret_cast<uintptr_t>(b) % al == 0 &&
                       reinterpret_cast<uintptr_t>(x) % al == 0;
+    const int rev = h->flip(l);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), c.child, c.ncol, c.nvp,
-                           b, x, bc, batch, kchunk, nkc, active);
+                           b, x, bc, batch, kchunk, nkc, active, rev);
     };
     // paired loads (the library's own buffers): streamed past the cache on
     // levels far larger than it
@@ -537,9 +542,10 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
     const int nkc = (h->nz + kApplyChunk - 1) / kApplyChunk;
     const dim3 grid(ntile * nkc * batch);
     const bool prof = (l == 0 && sizeof(T) == 8) && prof_begin(h, HELMHOLTZ_PROF_APPLY_FINE, s);
+    const int rev = h->flip(l);
     auto go = [&](auto kern) {
         hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), x, y, w, batch, nkc,
-                           cg_state(h), active);
+                           cg_state(h), active, rev);
     };
     if (h->weighted) {
         if (h->adj) {
@@ -997,10 +1003,27 @@ int create_impl(const helmholtz_config* cfg, const double* kh, const double* kv,
         if (hipMemcpyAsync(v.fface, ff.data(), 2 * nc * sizeof(uint32_t), hipMemcpyHostToDevice,
                            s) != hipSuccess)
             return fail(HELMHOLTZ_EHIP);
+        std::vector<int32_t> par, po;
         if (v.parent) {
-            std::vector<int32_t> par(nc);
+            par.resize(nc);
             build_parent(v.N, par.data());
             if (hipMemcpyAsync(v.parent, par.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice,
+                               s) != hipSuccess)
+                return fail(HELMHOLTZ_EHIP);
+            // prolongation offsets: the parent and the parents of the outward
+            // E/W (W for even i, E for odd i) and N/S (S for even j, N for
+            // odd j) neighbours, as tiled offsets on the coarse level
+            auto tb = [&](int32_t cc) { return (cc / kTile) * kTile * nz + cc % kTile; };
+            po.resize(3 * nc);
+            for (size_t c = 0; c < nc; ++c) {
+                const int i = int(c % v.N), j = int((c / v.N) % v.N);
+                const int32_t ew = tab[((i & 1) ? 0 : 1) * nc + c];
+                const int32_t ns = tab[((j & 1) ? 2 : 3) * nc + c];
+                po[c] = tb(par[c]);
+                po[nc + c] = tb(par[ew]);
+                po[2 * nc + c] = tb(par[ns]);
+            }
+            if (hipMemcpyAsync(v.pofs, po.data(), 3 * nc * sizeof(int32_t), hipMemcpyHostToDevice,
                                s) != hipSuccess)
                 return fail(HELMHOLTZ_EHIP);
         }
@@ -1218,17 +1241,19 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     // read again soon bypass it (see the kernels)
     const bool vnt = streams_past_cache(h, 0, batch, sizeof(double));
     auto dot_rz = [&](const double* q) {
+        const int rev = h->flip(0);
         auto go = [&](auto kern, auto z) {
-            hipLaunchKernelGGL(kern, red, blk, 0, s, h->r, z, q, n, kRedBlocks, st);
+            hipLaunchKernelGGL(kern, red, blk, 0, s, h->r, z, q, n, kRedBlocks, st, rev);
         };
         if (mixed) vnt ? go(k_dot_rz<float, true>, z32) : go(k_dot_rz<float, false>, z32);
         else vnt ? go(k_dot_rz<double, true>, h->z) : go(k_dot_rz<double, false>, h->z);
     };
     // p = z + beta p, with the x update owed from the last iteration (xmode)
     auto p_update = [&](int init, int xmode) {
+        const int rev = h->flip(0);
         auto go = [&](auto kern, auto z) {
             hipLaunchKernelGGL(kern, tgrid, blk, 0, s, z, h->p, x, v0.ncol, h->nz, v0.nvp, st,
-                               init, xmode);
+                               init, xmode, rev);
         };
         if (mixed) vnt ? go(k_p_update<float, true>, z32) : go(k_p_update<float, false>, z32);
         else vnt ? go(k_p_update<double, true>, h->z) : go(k_p_update<double, false>, h->z);
@@ -1241,12 +1266,13 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     p_update(1, kXNone);
     // the owed x update where the iteration stops (see k_cg_x)
     auto x_update = [&](int xmode, int only_done) {
+        const int rev = h->flip(0);
         if (vnt)
             hipLaunchKernelGGL(k_cg_x<true>, tgrid, blk, 0, s, x, h->p, v0.ncol, h->nz, v0.nvp,
-                               st, xmode, only_done);
+                               st, xmode, only_done, rev);
         else
             hipLaunchKernelGGL(k_cg_x<false>, tgrid, blk, 0, s, x, h->p, v0.ncol, h->nz, v0.nvp,
-                               st, xmode, only_done);
+                               st, xmode, only_done, rev);
     };
 
     const int ntile0 = (h->lev[0].ncol + kBlock - 1) / kBlock;
@@ -1262,12 +1288,13 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
         // r -= alpha q, ||r||^2 and the convergence flags, published; the
         // matching x += alpha p is owed (applied with the next p update, or
         // by x_update where the iteration stops)
+        const int rev = h->flip(0);
         if (vnt)
             hipLaunchKernelGGL(k_cg_update<true>, tgrid, blk, 0, s, h->r, r32, h->q, v0.ncol,
-                               h->nz, v0.nvp, st);
+                               h->nz, v0.nvp, st, rev);
         else
             hipLaunchKernelGGL(k_cg_update<false>, tgrid, blk, 0, s, h->r, r32, h->q, v0.ncol,
-                               h->nz, v0.nvp, st);
+                               h->nz, v0.nvp, st, rev);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinRR), ntile32, iter);
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
         if (int e = wait_published(h, s, was_active, iter)) return e;

@@ -24,6 +24,10 @@
 //                                      level 0 (plane * nvp + tile_base(owner));
 //                                      the E and N faces are at tile_base(c)
 //                                      and nvp + tile_base(c)
+//   pofs           [3][ncol]           tiled offsets on the next coarser level
+//                                      of the parent of the column and of the
+//                                      parents of its outward E/W and N/S
+//                                      neighbours (prolongation)
 // A workgroup that owns a tile reads one contiguous block of every array and
 // a wave reads two adjacent rows of one tile. Vectors passed through the C ABI
 // keep the natural [batch][nz][ncol] layout; the kernels that take them in or
@@ -62,11 +66,21 @@ constexpr int kBlock = 256;
 // Workgroups of one launch are handed to the 8 XCDs round-robin (bid -> XCD
 // bid % 8). Renumber them so that each XCD works through one contiguous range
 // of logical blocks: neighbouring tiles (the N/S neighbour rows, the batch
-// members sharing coefficients) then meet in the same L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+// members sharing coefficients) then meet in the same L2. rev: each XCD walks
+// its range backwards. Consecutive kernels on a level alternate the direction,
+// so that each starts on the data the previous one touched last, which the
+// last-level cache still holds when a level's streams exceed it.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks, int rev = 0) {
     const int xcd = bid & 7, slot = bid >> 3;
     const int q = nblocks >> 3, r = nblocks & 7;
-    return xcd * q + (xcd < r ? xcd : r) + slot;
+    const int cnt = q + (xcd < r ? 1 : 0);
+    return xcd * q + (xcd < r ? xcd : r) + (rev ? cnt - 1 - slot : slot);
+}
+
+// Logical block of a launch without the XCD renumbering, walked backwards
+// when rev is set.
+__device__ __forceinline__ int logical_block(int rev) {
+    return rev ? int(gridDim.x) - 1 - int(blockIdx.x) : int(blockIdx.x);
 }
 
 constexpr int kTile = 32;
@@ -79,8 +93,13 @@ __device__ __forceinline__ int tile_base(int c, int nz) {
 template <typename T>
 struct LevelView {
     int ncol, nz, nvp;
+    int N;  // columns per panel edge (c = p N^2 + j N + i)
     const int32_t* __restrict__ nbr;
     const uint32_t* __restrict__ fface;
+    // [3][ncol] on every level but the coarsest: tiled offsets on the next
+    // coarser level of the column's parent and of the parents of its outward
+    // E/W and N/S neighbours (the other two neighbours share its parent)
+    const int32_t* __restrict__ pofs;
     const T* __restrict__ kh;
     const T* __restrict__ kv;
     const T* __restrict__ dl;
@@ -270,8 +289,9 @@ template <typename T, int JMAX, int MODE, int TC_ = SweepTile<T>::TC, int NT = k
 __global__ void __launch_bounds__(NT)
 __attribute__((amdgpu_waves_per_eu(SweepWaves<T, JMAX, MODE, K2, SC>::value)))
 k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
-        const T* __restrict__ xc, const int32_t* __restrict__ parent, int nvp_c,
-        T* __restrict__ y, T omega, int batch, const int* __restrict__ active, int mid) {
+        const T* __restrict__ xc, int nvp_c,
+        T* __restrict__ y, T omega, int batch, const int* __restrict__ active, int mid,
+        int rev) {
     constexpr int TC = TC_, KG = NT / TC;
     constexpr int BOT = (TC + 63) / 64 * 64;  // first lane of the bottom elimination (own wave)
     static_assert(BOT + TC <= NT, "two elimination lane groups must fit the workgroup");
@@ -286,7 +306,7 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     T* E1 = Cf + nz * TC;                   // [TC]: cc_{mid-1} t_{mid-1}
     T* E2 = E1 + TC;                        // [TC]: cc_{mid+1} t_{mid+1}
 
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int lb = xcd_remap(blockIdx.x, gridDim.x, rev);
     const int rhs = lb % batch, tile = lb / batch;
     if (active && !active[rhs]) return;
     const int tid = threadIdx.x;
@@ -302,29 +322,37 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
     const int ob = tile_base(c, nz);
 
     // ---- phase 1: right-hand side and factors into LDS --------------------
-    // nb: tiled offsets of the neighbours (and of the parents on the coarse
-    // level, pn); fW, fS: offsets of the W and S faces in kh.
-    int nb[4] = {0, 0, 0, 0}, pn[5] = {0, 0, 0, 0, 0};
+    // nb: tiled offsets of the neighbours; fW, fS: offsets of the W and S
+    // faces in kh. Prolongation: the coarse values of the column's parent (pP)
+    // and of the parents of its outward E/W (pX) and N/S (pY) neighbours; the
+    // E neighbour is outward for odd i, the N neighbour for odd j, and the
+    // other neighbour of each pair shares the column's parent.
+    int nb[4] = {0, 0, 0, 0};
+    int pP = 0, pX = 0, pY = 0;
+    bool eOut = false, nOut = false;
     uint32_t fW = 0, fS = 0;
     if (MODE != kZero && valid) {
 #pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            const int cn = L.nbr[d * ncol + c];
-            nb[d] = tile_base(cn, nz);
-            if (kHasP) pn[d] = tile_base(parent[cn], nz);
-        }
+        for (int d = 0; d < 4; ++d) nb[d] = tile_base(L.nbr[d * ncol + c], nz);
         fW = L.fface[c];
         fS = L.fface[ncol + c];
-        if (kHasP) pn[4] = tile_base(parent[c], nz);
+        if (kHasP) {
+            pP = L.pofs[c];
+            pX = L.pofs[ncol + c];
+            pY = L.pofs[2 * ncol + c];
+            eOut = ((c % L.N) & 1) != 0;
+            nOut = (((c / L.N) % L.N) & 1) != 0;
+        }
     }
     auto ld = [](const T* p) -> T {
         if constexpr (NTS) return __builtin_nontemporal_load(p);
         else return *p;
     };
-    auto xv = [&](int k, int off, int poff) -> T {
+    // the iterate after the prolongation at level k of the column itself
+    auto xown = [&](int k) -> T {
         T v = T(0);
-        if (kHasX) v = x[off + kTile * k];
-        if (kHasP) v += xc[poff + kTile * k];
+        if (kHasX) v = x[ob + kTile * k];
+        if (kHasP) v += xc[pP + kTile * k];
         return v;
     };
     // Loads of CH levels are issued together before any is used, so each
@@ -361,16 +389,34 @@ k_sweep(LevelView<T> L, const T* __restrict__ b, const T* __restrict__ x,
                     vk[jj][1] = L.kh[fW + uint32_t(kTile * k)];
                     vk[jj][2] = khN[o];
                     vk[jj][3] = L.kh[fS + uint32_t(kTile * k)];
+                    T cP = T(0), cX = T(0), cY = T(0);
+                    if constexpr (kHasP) {
+                        cP = xc[pP + kTile * k];
+                        cX = xc[pX + kTile * k];
+                        cY = xc[pY + kTile * k];
+                    }
+                    const T pe[4] = {eOut ? cX : cP, eOut ? cP : cX, nOut ? cY : cP,
+                                     nOut ? cP : cY};
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) vx[jj][d] = xv(k, nb[d], pn[d]);
-                    vx[jj][4] = xv(k, ob, pn[4]);
+                    for (int d = 0; d < 4; ++d) {
+                        T v = T(0);
+                        if (kHasX) v = x[nb[d] + kTile * k];
+                        if (kHasP) v += pe[d];
+                        vx[jj][d] = v;
+                    }
+                    {
+                        T v = T(0);
+                        if (kHasX) v = x[ob + kTile * k];
+                        if (kHasP) v += cP;
+                        vx[jj][4] = v;
+                    }
                     if constexpr (SC == kRowWT) {
 #pragma unroll
                         for (int d = 0; d < 4; ++d) vsn[jj][d] = L.s[nb[d] + kTile * k];
                     }
                     if constexpr (K2) {
-                        if (k + 2 < nz) v2[jj] = L.kv2[o] * xv(k + 2, ob, pn[4]);
-                        if (k >= 2) v2[jj] += L.kv2[o - 2 * kTile] * xv(k - 2, ob, pn[4]);
+                        if (k + 2 < nz) v2[jj] = L.kv2[o] * xown(k + 2);
+                        if (k >= 2) v2[jj] += L.kv2[o - 2 * kTile] * xown(k - 2);
                     }
                 }
             }
@@ -597,9 +643,9 @@ enum { kDotNone = 0, kDotXY = 1, kDotWY = 2, kDotWYYY = 3 };
 template <typename T, int DOT, int KC, bool K2 = false, int SC = kSym, bool NTS = false>
 __global__ void __launch_bounds__(kBlock)
 k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
-        int batch, int nkc, CgState st, const int* __restrict__ active) {
+        int batch, int nkc, CgState st, const int* __restrict__ active, int rev) {
     __shared__ double sh[kBlock / 64];
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+    const int lb = xcd_remap(blockIdx.x, gridDim.x, rev);
     const int rhs = lb % batch, rest = lb / batch;
     const int kc = rest % nkc, tile = rest / nkc;
     if (active && !active[rhs]) return;
@@ -777,8 +823,8 @@ template <typename T, bool ZEROX, bool PAIR, bool K2 = false, int SC = kSym, boo
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
                  const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
-                 int batch, int kchunk, int nkc, const int* __restrict__ active) {
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
+                 int batch, int kchunk, int nkc, const int* __restrict__ active, int rev) {
+    const int lb = xcd_remap(blockIdx.x, gridDim.x, rev);
     const int rhs = lb % batch, rest = lb / batch;
     const int kc = rest % nkc, tile = rest / nkc;
     if (active && !active[rhs]) return;
@@ -1136,11 +1182,12 @@ struct TileGrid {
     int rhs, tile, lc, g, c;
     bool valid;
 };
-__device__ __forceinline__ TileGrid tile_grid(int ncol) {
+__device__ __forceinline__ TileGrid tile_grid(int ncol, int rev = 0) {
     const int ntile = (ncol + kTile - 1) / kTile;
+    const int lb = logical_block(rev);
     TileGrid t;
-    t.rhs = blockIdx.x / ntile;
-    t.tile = blockIdx.x % ntile;
+    t.rhs = lb / ntile;
+    t.tile = lb % ntile;
     t.lc = threadIdx.x & (kTile - 1);
     t.g = threadIdx.x / kTile;
     t.c = t.tile * kTile + t.lc;
@@ -1194,9 +1241,9 @@ k_cg_zero_idle(double* __restrict__ x, int ncol, int nz, CgState st) {
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_cg_update(double* __restrict__ r, float* __restrict__ r32, const double* __restrict__ q,
-            int ncol, int nz, int nvp, CgState st) {
+            int ncol, int nz, int nvp, CgState st, int rev) {
     __shared__ double sh[kBlock / 64];
-    const TileGrid t = tile_grid(ncol);
+    const TileGrid t = tile_grid(ncol, rev);
     if (!st.active[t.rhs]) return;
     const double alpha = st.sc[t.rhs * kScal + kAlpha];
     double acc = 0.0;
@@ -1224,8 +1271,8 @@ enum { kXNone = 0, kXSet = 1, kXAdd = 2 };
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_cg_x(double* __restrict__ x, const double* __restrict__ p, int ncol, int nz, int nvp,
-       CgState st, int xmode, int only_done) {
-    const TileGrid t = tile_grid(ncol);
+       CgState st, int xmode, int only_done, int rev) {
+    const TileGrid t = tile_grid(ncol, rev);
     if (!t.valid || !st.upd[t.rhs] || (only_done && st.active[t.rhs])) return;
     const double alpha = st.sc[t.rhs * kScal + kAlpha];
     const int64_t ia = t.rhs * int64_t(nz) * ncol + t.c;
@@ -1258,9 +1305,10 @@ k_retile(const S* __restrict__ src, D* __restrict__ dst, int ncol, int nz, int n
 template <typename Z, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __restrict__ q,
-         int64_t n, int nblk, CgState st) {
+         int64_t n, int nblk, CgState st, int rev) {
     __shared__ double sh[kBlock / 64];
-    const int rhs = blockIdx.x / nblk, blk = blockIdx.x % nblk;
+    const int lbk = logical_block(rev);
+    const int rhs = lbk / nblk, blk = lbk % nblk;
     if (!st.active[rhs]) return;
     int64_t i0, i1;
     grid_range(n, nblk, blk, i0, i1);
@@ -1289,8 +1337,8 @@ k_dot_rz(const double* __restrict__ r, const Z* __restrict__ z, const double* __
 template <typename Z, bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_p_update(const Z* __restrict__ z, double* __restrict__ p, double* __restrict__ x, int ncol,
-           int nz, int nvp, CgState st, int init, int xmode) {
-    const TileGrid t = tile_grid(ncol);
+           int nz, int nvp, CgState st, int init, int xmode, int rev) {
+    const TileGrid t = tile_grid(ncol, rev);
     if (!t.valid || !st.active[t.rhs]) return;
     const double beta = init ? 0.0 : st.sc[t.rhs * kScal + kBeta];
     const double alpha = xmode != kXNone ? st.sc[t.rhs * kScal + kAlpha] : 0.0;
