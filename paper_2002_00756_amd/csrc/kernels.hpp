@@ -921,6 +921,8 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
             load_pair<T, PAIR>(F.kv2, r1 + cb[2], k2m1[2], k2m1[3]);
         }
     }
+    // two levels per step: the loads of the second are issued with the first's
+#pragma unroll 2
     for (int k = k0; k < k1; ++k) {
         const int r = kTile * k;
         T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8];
