@@ -512,8 +512,8 @@ def main():
                     help="skip the pressure-solver configurations of Section 5.1 and the "
                          "CFL robustness study")
     ap.add_argument("--probe", action="store_true",
-                    help="for counter runs: a few solves plus a 1 GiB device copy of known "
-                         "size, no JSON")
+                    help="for counter runs: a few solves (of the workload's whole batch) plus "
+                         "a 1 GiB device copy of known size, no JSON")
     ap.add_argument("--cpu-baseline-worker", metavar="OUTDIR", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_baseline_worker:
@@ -580,8 +580,18 @@ def main():
         return e0.elapsed_time(e1) / steps, wall / steps * 1e3, its, res
 
     if args.probe:
-        for _ in range(max(args.steps, 1)):
-            op32.solve(b, rtol=args.rtol, out=x)
+        if w.batch > 1:
+            # the workload's batch of right-hand sides through one handle
+            del op32, op64
+            torch.cuda.empty_cache()
+            opb = Operator(w.N, w.nz, kh_d, kv_d, dl_d, w.nlevels, precision="fp32",
+                           cg=args.cg, max_batch=w.batch, device=dev, **prm)
+            bb = torch.from_numpy(workloads.rhs(w.N, w.nz, w.batch)).to(dev)
+            for _ in range(max(args.steps, 1)):
+                opb.solve(bb, rtol=args.rtol)
+        else:
+            for _ in range(max(args.steps, 1)):
+                op32.solve(b, rtol=args.rtol, out=x)
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
