@@ -658,6 +658,31 @@ def main():
     torch.cuda.synchronize()
     adj_ms = (time.perf_counter() - t) / reps_adj * 1e3
 
+    # --- the differentiable solve: loss = g . x, forward + backward ----------
+    # (the first call builds the operator; later ones take it from the pool
+    # and replace its coefficients)
+    from paper_2002_00756_amd import autograd as hh_autograd, helmholtz_solve
+    leaves = [t_.clone().requires_grad_(True) for t_ in (kh_d, kv_d, dl_d)]
+
+    def diff_step():
+        xs = helmholtz_solve(b, *leaves, N=w.N, nz=w.nz, nlevels=w.nlevels,
+                             precision="fp32", rtol=args.rtol, **prm)
+        (g * xs).sum().backward()
+
+    hh_autograd.clear_operator_pool()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    diff_step()
+    torch.cuda.synchronize()
+    diff_first_ms = (time.perf_counter() - t) * 1e3
+    t = time.perf_counter()
+    for _ in range(reps_adj):
+        diff_step()
+    torch.cuda.synchronize()
+    diff_ms = (time.perf_counter() - t) / reps_adj * 1e3
+    del leaves
+    hh_autograd.clear_operator_pool()
+
     ref = stream_reference(torch, dev, lib, _lib.check)
     stream_gbs = ref["best_GBps"]
 
@@ -749,6 +774,10 @@ def main():
         "stream_reference": ref,
         "setup_ms": setup_ms,
         "adjoint_step_ms": adj_ms,
+        "autograd_step_ms": {"first": diff_first_ms, "reused": diff_ms,
+                             "note": "helmholtz_solve(b, kh, kv, delta) forward + backward of "
+                                     "g . x; the first call builds the operator, later ones "
+                                     "reuse it with helmholtz_update"},
     }
     out["vcycle_in_solve"]["fp32"]["frac_of_stream"] = \
         out["vcycle_in_solve"]["fp32"]["GBps"] / stream_gbs
