@@ -1268,14 +1268,18 @@ k_cg_update(double* __restrict__ r, float* __restrict__ r32, const double* __res
 enum { kXNone = 0, kXSet = 1, kXAdd = 2 };
 
 // The owed x update where the iteration stops: for the right-hand sides that
-// the last residual update included (upd) and, with only_done, that have
-// converged in it. NT: x bypasses the cache.
+// the last residual update included (upd) and that `sel` names: kXAll all of
+// them, kXDone those that have converged in it, kXLive the others. NT: x
+// bypasses the cache.
+enum { kXAll = 0, kXDone = 1, kXLive = 2 };
+
 template <bool NT>
 __global__ void __launch_bounds__(kBlock)
 k_cg_x(double* __restrict__ x, const double* __restrict__ p, int ncol, int nz, int nvp,
-       CgState st, int xmode, int only_done, int rev) {
+       CgState st, int xmode, int sel, int rev) {
     const TileGrid t = tile_grid(ncol, rev);
-    if (!t.valid || !st.upd[t.rhs] || (only_done && st.active[t.rhs])) return;
+    if (!t.valid || !st.upd[t.rhs]) return;
+    if ((sel == kXDone && st.active[t.rhs]) || (sel == kXLive && !st.active[t.rhs])) return;
     const double alpha = st.sc[t.rhs * kScal + kAlpha];
     const int64_t ia = t.rhs * int64_t(nz) * ncol + t.c;
     const int64_t it = t.rhs * int64_t(nvp) + tile_base(t.c, nz);
