@@ -776,7 +776,7 @@ int precondition_into(helmholtz_s* h, const double* u, double* out, int batch, c
 // with H and two V-cycles; the inner products (r0, v), (t, s) with (t, t),
 // and (r0, r) with ||r||^2 are the four global sums of Section 3.7. it/rel
 // are updated for every right-hand side that was active in an iteration.
-int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
+int bicgstab_loop(helmholtz_s* h, double* x, int batch, double rtol, int maxiter,
                   const std::vector<double>& bnorm2, std::vector<int32_t>& it,
                   std::vector<double>& rel, hipStream_t s) {
     const Level& v0 = h->lev[0];
@@ -788,8 +788,13 @@ int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
     const CgState st = cg_state(h);
     std::vector<int> was_active(batch);
     bool broke = false;
-    for (int iter = 1;; ++iter) {
-        for (int i = 0; i < batch; ++i) was_active[i] = h->hact[i];
+    // Everything of an iteration up to its x and r update skips the
+    // right-hand sides whose device flag the last norm cleared, so, as in CG,
+    // it is queued before the host reads that norm when the norm is predicted
+    // to stay above 4x the tolerance (the update and the published norm are
+    // queued after the read: the host mirror holds one iteration's values).
+    const bool ahead = !h->prof_on;
+    auto first_half = [&](int iter) -> int {
         // p = r + beta (p - omega v); p_hat = M p; v = H p_hat; alpha = rho / (r0, v)
         hipLaunchKernelGGL(k_bicg_p, red, blk, 0, s, h->r, h->q, h->p, n, kRedBlocks, h->sc,
                            h->active, iter == 1 ? 1 : 0);
@@ -804,10 +809,24 @@ int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
         launch_apply<double>(h, 0, h->sh, h->t, batch, kDotWYYY, h->active, s, h->s);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBiOmega),
                            ntile0 * nkc0, 0);
+        return last_error();
+    };
+    std::vector<double> fac(batch, 0.05), rel_prev(batch, 1.0);
+    auto expect_more = [&]() {
+        for (int i = 0; i < batch; ++i)
+            if (h->hact[i] && rel_prev[i] * fac[i] > 4.0 * rtol) return true;
+        return false;
+    };
+    if (int e = first_half(1)) return e;
+    for (int iter = 1;; ++iter) {
+        for (int i = 0; i < batch; ++i) was_active[i] = h->hact[i];
         // x += alpha p_hat + omega s_hat; r = s - omega t; (r0, r), ||r||^2, published
         hipLaunchKernelGGL(k_bicg_xr, tgrid, blk, 0, s, x, h->r, h->z, h->sh, h->s, h->t, h->r0,
                            v0.ncol, h->nz, v0.nvp, st);
         hipLaunchKernelGGL(k_finalize, dim3(batch), fin, 0, s, st, int(kFinBiRR), ntile32, iter);
+        const bool queued = ahead && iter < maxiter && expect_more();
+        if (queued)
+            if (int e = first_half(iter + 1)) return e;
         if (last_error() != HELMHOLTZ_OK) return HELMHOLTZ_EHIP;
         if (int e = wait_published(h, s, was_active, iter)) return e;
         bool still = false;
@@ -815,8 +834,13 @@ int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
             if (!was_active[i]) continue;
             it[i] = iter;
             const double rr = h->hsc[i * kScal + kRR];
-            if (!std::isfinite(rr)) return HELMHOLTZ_ENONFINITE;
+            if (!std::isfinite(rr)) {
+                HH_CHECK(hipStreamSynchronize(s));
+                return HELMHOLTZ_ENONFINITE;
+            }
             rel[i] = std::sqrt(rr / bnorm2[i]);
+            fac[i] = rel[i] / rel_prev[i];
+            rel_prev[i] = rel[i];
             broke = broke || h->hsc[i * kScal + kBreak] != 0.0;
             still = still || h->hact[i];
         }
@@ -825,6 +849,8 @@ int bicgstab_loop(helmholtz_s* h, double* x, int batch, int maxiter,
             broke = true;
             break;
         }
+        if (!queued)
+            if (int e = first_half(iter + 1)) return e;
     }
     // the caller may read x as soon as this returns on the host
     HH_CHECK(hipStreamSynchronize(s));
@@ -1309,7 +1335,7 @@ int helmholtz_solve(helmholtz_t h, const double* b, double* x, int32_t batch, do
     if (!finite || !any) HH_CHECK(hipStreamSynchronize(s));
     if (!finite) return HELMHOLTZ_ENONFINITE;
     if (!any) return finish(HELMHOLTZ_OK);
-    if (bicg) return finish(bicgstab_loop(h, x, batch, maxiter, bnorm2, it, rel, s));
+    if (bicg) return finish(bicgstab_loop(h, x, batch, rtol, maxiter, bnorm2, it, rel, s));
     if (!ahead)
         if (int e = cg_start()) return e;
 
