@@ -534,6 +534,11 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
             pick(k_resid_restrict<T, false, true, false, kRowW>,
                  k_resid_restrict<T, false, true, false, kRowW, true>);
         else go(k_resid_restrict<T, false, false, false, kRowW>);
+    } else if (pair && c.N % 32 == 0) {
+        // the coarse panels tile into patches: children's values through LDS
+        pick(k_resid_restrict_lds<T, false, 32>, k_resid_restrict_lds<T, true, 32>);
+    } else if (pair && c.N % 16 == 0) {
+        pick(k_resid_restrict_lds<T, false, 16>, k_resid_restrict_lds<T, true, 16>);
     } else {
         if (pair)
             pick(k_resid_restrict<T, false, true>,

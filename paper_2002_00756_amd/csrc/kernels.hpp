@@ -1010,6 +1010,168 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
     }
 }
 
+// Residual and restriction with the children's values exchanged in LDS (the
+// symmetric 7-point operator on coarse panels whose width is a multiple of
+// PX). One workgroup owns a PX x PY patch of coarse cells of one panel
+// (PX PY = kBlock) and a chunk of levels; thread t = pi + PX pj owns cell
+// (I, J) of the patch, whose W, E, S, N neighbours are threads t - 1, t + 1,
+// t - PX, t + PX (inside a panel the E, N neighbour of column (i, j) is
+// (i + 1, j), (i, j + 1), and cell (I, J) has children (2I + di, 2J + dj)).
+// At every level each thread publishes the x of its four children and the
+// faces it owns (E faces of its east children, N faces of its north
+// children); the eight outer x and four outer faces a cell needs then come
+// from its neighbours, and only the cells on the patch's edges read theirs
+// from global memory. In k_resid_restrict those reads are gathers from rows
+// that other waves or workgroups load at other times, and a third of them
+// found the line gone from L2 (1.28x the kernel's words at C192 x 70). A
+// patch twice as wide as high (32 x 8) has half the W and E edge cells of a
+// square one, each of which reads a whole line for one value: at C192 x 70,
+// float32, 88.7 us (k_resid_restrict) -> 76.6 (16 x 16) -> 71.8 us (32 x 8).
+// Same arithmetic, in the same order, as k_resid_restrict: the results are
+// identical.
+template <typename T, bool NTS, int PX>
+__global__ void __launch_bounds__(kBlock)
+k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
+                     const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
+                     int batch, int kchunk, int nkc, const int* __restrict__ active, int rev) {
+    // [level parity][value][thread]: x of children 00, 10, 01, 11; then the E
+    // faces of 10, 11 and the N faces of 01, 11
+    __shared__ T lx[2][4][kBlock];
+    __shared__ T lf[2][4][kBlock];
+    constexpr int PY = kBlock / PX;
+    static_assert(PX * PY == kBlock, "a patch is one workgroup");
+    const int lb = xcd_remap(blockIdx.x, gridDim.x, rev);
+    const int rhs = lb % batch, rest = lb / batch;
+    const int kc = rest % nkc, tile = rest / nkc;
+    if (active && !active[rhs]) return;  // the whole workgroup
+    const int t = threadIdx.x, pi = t % PX, pj = t / PX;
+    const int Nc = F.N >> 1, pwx = Nc / PX, npp = pwx * (Nc / PY);
+    const int pan = tile / npp, q = tile % npp;
+    // every cell of a patch exists (ncol_c = 6 Nc^2 is a multiple of kBlock),
+    // so no thread leaves before the barriers
+    const int C = (pan * Nc + (q / pwx) * PY + pj) * Nc + (q % pwx) * PX + pi;
+    const bool eW = pi == 0, eE = pi == PX - 1, eS = pj == 0, eN = pj == PY - 1;
+    const int ncol = F.ncol, nz = F.nz;
+    const int64_t nv = F.nvp;
+    b += rhs * nv;
+    x += rhs * nv;
+    bc += rhs * int64_t(nvp_c) + tile_base(C, nz);
+    auto load_once = [](const T* p, int64_t i, T& a, T& c) {
+        if constexpr (NTS) load_pair_nt<T, true>(p, i, a, c);
+        else load_pair<T, true>(p, i, a, c);
+    };
+    int ch[4], cb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        ch[s] = child[s * ncol_c + C];
+        cb[s] = tile_base(ch[s], nz);
+    }
+    // outer x and faces from global memory, for the patch's edge cells only
+    // (the numbering of k_resid_restrict: f = 2 child + {0: W or E, 1: S or N})
+    int out[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t fc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (eW) {
+        out[0] = tile_base(F.nbr[1 * ncol + ch[0]], nz); fc[0] = F.fface[ch[0]];
+        out[4] = tile_base(F.nbr[1 * ncol + ch[2]], nz); fc[4] = F.fface[ch[2]];
+    }
+    if (eE) {
+        out[2] = tile_base(F.nbr[0 * ncol + ch[1]], nz);
+        out[6] = tile_base(F.nbr[0 * ncol + ch[3]], nz);
+    }
+    if (eS) {
+        out[1] = tile_base(F.nbr[3 * ncol + ch[0]], nz); fc[1] = F.fface[ncol + ch[0]];
+        out[3] = tile_base(F.nbr[3 * ncol + ch[1]], nz); fc[3] = F.fface[ncol + ch[1]];
+    }
+    if (eN) {
+        out[5] = tile_base(F.nbr[2 * ncol + ch[2]], nz);
+        out[7] = tile_base(F.nbr[2 * ncol + ch[3]], nz);
+    }
+    const int k0 = kc * kchunk, k1 = min(nz, k0 + kchunk);
+    T xdn[4] = {T(0), T(0), T(0), T(0)}, xo[4], kvdn[4] = {T(0), T(0), T(0), T(0)};
+    if (k0 > 0) {
+        const int rdn = kTile * (k0 - 1);
+        load_pair<T, true>(x, rdn + cb[0], xdn[0], xdn[1]);
+        load_pair<T, true>(x, rdn + cb[2], xdn[2], xdn[3]);
+        load_pair<T, true>(F.kv, rdn + cb[0], kvdn[0], kvdn[1]);
+        load_pair<T, true>(F.kv, rdn + cb[2], kvdn[2], kvdn[3]);
+    }
+    load_pair<T, true>(x, kTile * k0 + cb[0], xo[0], xo[1]);
+    load_pair<T, true>(x, kTile * k0 + cb[2], xo[2], xo[3]);
+    for (int k = k0; k < k1; ++k) {
+        const int r = kTile * k, buf = k & 1;
+        T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8], unused;
+        if (k + 1 < nz) {
+            load_pair<T, true>(x, r + kTile + cb[0], xup[0], xup[1]);
+            load_pair<T, true>(x, r + kTile + cb[2], xup[2], xup[3]);
+        }
+        load_once(b, r + cb[0], vb[0], vb[1]);
+        load_once(b, r + cb[2], vb[2], vb[3]);
+        load_once(F.dl, r + cb[0], vd[0], vd[1]);
+        load_once(F.dl, r + cb[2], vd[2], vd[3]);
+        load_pair<T, true>(F.kv, r + cb[0], vkv[0], vkv[1]);
+        load_pair<T, true>(F.kv, r + cb[2], vkv[2], vkv[3]);
+        // own faces: E of 10 and 11 (the E of 00, 01 is between siblings), N of 01, 11
+        load_pair<T, true>(F.kh, r + cb[0], unused, vk[2]);
+        load_pair<T, true>(F.kh, r + cb[2], unused, vk[6]);
+        load_pair<T, true>(F.kh + nv, r + cb[2], vk[5], vk[7]);
+        if (eW) {
+            vxo[0] = x[out[0] + r]; vk[0] = F.kh[fc[0] + uint32_t(r)];
+            vxo[4] = x[out[4] + r]; vk[4] = F.kh[fc[4] + uint32_t(r)];
+        }
+        if (eE) {
+            vxo[2] = x[out[2] + r];
+            vxo[6] = x[out[6] + r];
+        }
+        if (eS) {
+            vxo[1] = x[out[1] + r]; vk[1] = F.kh[fc[1] + uint32_t(r)];
+            vxo[3] = x[out[3] + r]; vk[3] = F.kh[fc[3] + uint32_t(r)];
+        }
+        if (eN) {
+            vxo[5] = x[out[5] + r];
+            vxo[7] = x[out[7] + r];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) lx[buf][s][t] = xo[s];
+        lf[buf][0][t] = vk[2];
+        lf[buf][1][t] = vk[6];
+        lf[buf][2][t] = vk[5];
+        lf[buf][3][t] = vk[7];
+        // the writes of level k - 1's buffer were read before the last barrier
+        __syncthreads();
+        if (!eW) {
+            vxo[0] = lx[buf][1][t - 1]; vk[0] = lf[buf][0][t - 1];
+            vxo[4] = lx[buf][3][t - 1]; vk[4] = lf[buf][1][t - 1];
+        }
+        if (!eE) {
+            vxo[2] = lx[buf][0][t + 1];
+            vxo[6] = lx[buf][2][t + 1];
+        }
+        if (!eS) {
+            vxo[1] = lx[buf][2][t - PX]; vk[1] = lf[buf][2][t - PX];
+            vxo[3] = lx[buf][3][t - PX]; vk[3] = lf[buf][3][t - PX];
+        }
+        if (!eN) {
+            vxo[5] = lx[buf][0][t + PX];
+            vxo[7] = lx[buf][1][t + PX];
+        }
+        T acc = ((vb[0] + vb[1]) + vb[2]) + vb[3];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            acc -= vd[s] * xo[s];
+            acc -= vkv[s] * (xo[s] - xup[s]) + kvdn[s] * (xo[s] - xdn[s]);
+        }
+#pragma unroll
+        for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
+        bc[r] = acc;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            xdn[s] = xo[s];
+            xo[s] = xup[s];
+            kvdn[s] = vkv[s];
+        }
+    }
+}
+
 // Prolongation by natural injection on its own (only when there is no
 // post-smoothing sweep to fuse it into): y = x + xc[parent] (x may be null).
 template <typename T>

@@ -49,6 +49,10 @@ CASES = [
     (24, 30, 4, 1.0, 1000.0, True),
     (6, 70, 2, 1.0, 1000.0, True),
     (16, 120, 5, 2.0, 10.0, False),
+    # the residual restriction in coarse patches staged through LDS: 16 x 16
+    # patches (coarse panel width 16), 32 x 8 then 16 x 16 (widths 32, 16)
+    (32, 8, 3, 1.0, 1000.0, True),
+    (64, 6, 3, 1.0, 100.0, False),
 ]
 
 
@@ -88,13 +92,13 @@ def test_vcycle_parameter_variants(prm):
     assert _rel(x, multigrid.vcycle(hier, b, prm)) <= 1e-10
 
 
-@pytest.mark.parametrize("N,nz,L", [(12, 10, 3), (24, 30, 4), (8, 70, 4)])
+@pytest.mark.parametrize("N,nz,L", [(12, 10, 3), (24, 30, 4), (8, 70, 4), (64, 6, 3)])
 def test_vcycle_fp32(N, nz, L):
     """Float32 V-cycle against the float32 emulation and the float64 V-cycle.
 
     Gates (max-norm, relative): about three times the largest errors measured
     on MI355X over these cases (float32 V-cycle vs the float64 oracle 2.0e-7,
-    vs the float32 emulation 5.3e-7, float64 entry point of a float32 handle
+    vs the float32 emulation 5.9e-7, float64 entry point of a float32 handle
     2.0e-7). The a-priori bound, the columns' condition number (up to about
     4 kv / delta = 4e3) times the float32 rounding 6e-8, is 2.4e-4.
     """
