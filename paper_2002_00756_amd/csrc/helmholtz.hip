@@ -583,6 +583,24 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
             case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk, true>); break;
             default: go(k_apply<T, kDotNone, kApplyChunk, true>); break;
         }
+    } else if (v.N % kTile == 0) {
+        // the panels tile into patches of 64 x 4 (else 32 x 8) columns:
+        // neighbours' values through LDS
+        auto patch = [&](auto nts, auto px) {
+            constexpr bool NT = decltype(nts)::value;
+            constexpr int PX = decltype(px)::value;
+            switch (dot) {
+                case kDotXY: go(k_apply_lds<T, kDotXY, kApplyChunk, NT, PX>); break;
+                case kDotWY: go(k_apply_lds<T, kDotWY, kApplyChunk, NT, PX>); break;
+                case kDotWYYY: go(k_apply_lds<T, kDotWYYY, kApplyChunk, NT, PX>); break;
+                default: go(k_apply_lds<T, kDotNone, kApplyChunk, NT, PX>); break;
+            }
+        };
+        using P64 = std::integral_constant<int, 64>;
+        using P32 = std::integral_constant<int, 32>;
+        const bool nt = streams_past_cache(h, l, batch, sizeof(T));
+        if (v.N % 64 == 0) nt ? patch(std::true_type{}, P64{}) : patch(std::false_type{}, P64{});
+        else nt ? patch(std::true_type{}, P32{}) : patch(std::false_type{}, P32{});
     } else if (streams_past_cache(h, l, batch, sizeof(T))) {
         switch (dot) {
             case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, false, kSym, true>); break;

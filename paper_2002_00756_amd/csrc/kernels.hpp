@@ -767,6 +767,144 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
     }
 }
 
+// The operator apply of the symmetric 7-point operator with the neighbours'
+// values exchanged in LDS (panels whose width is a multiple of PX, 32 or 64).
+// One workgroup owns a PX x PY patch of columns of one panel
+// (PX PY = kBlock, each patch row one storage tile) and a chunk of KC levels;
+// thread t = pi + PX pj owns column (i, j), whose W, E, S, N neighbours are
+// threads t - 1, t + 1, t - PX, t + PX. All loads of the chunk are issued
+// first; then each thread publishes its x and its E and N faces (the W face
+// of a column is the E face of its W neighbour, the S face the N face of its S
+// neighbour) and, after one barrier, takes its neighbours' values from LDS;
+// only the patch's edge columns gather from global memory. In k_apply those
+// gathers cost 31 of 172 us at C192 x 70 (measured by skipping them): the N
+// and S ones often miss L2, and the E and W ones, shifted by one element,
+// touch an extra line per wave. Here: 162 us with 64 x 4 patches, 163 with
+// 32 x 8 (patches walked column by column: 168 us). y is computed by the same
+// expression as in k_apply and is identical; the partial sums of the dot
+// products follow the patches.
+template <typename T, int DOT, int KC, bool NTS, int PX>
+__global__ void __launch_bounds__(kBlock)
+k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
+            int batch, int nkc, CgState st, const int* __restrict__ active, int rev) {
+    constexpr int PY = kBlock / PX;
+    static_assert(PX * PY == kBlock && PX % kTile == 0, "patch rows are whole storage tiles");
+    __shared__ T lx[KC][kBlock];   // x at k0 .. k0 + KC - 1
+    __shared__ T lfe[KC][kBlock];  // E faces
+    __shared__ T lfn[KC][kBlock];  // N faces
+    __shared__ double sh[kBlock / 64];
+    const int lb = xcd_remap(blockIdx.x, gridDim.x, rev);
+    const int rhs = lb % batch, rest = lb / batch;
+    const int kc = rest % nkc, tile = rest / nkc;
+    if (active && !active[rhs]) return;  // the whole workgroup
+    const int t = threadIdx.x, pi = t % PX, pj = t / PX;
+    const int N = L.N, pwx = N / PX, npp = pwx * (N / PY);
+    const int pan = tile / npp, q = tile % npp;
+    // every column of a patch exists, so no thread leaves before the barrier
+    const int c = (pan * N + (q / pwx) * PY + pj) * N + (q % pwx) * PX + pi;
+    const bool eW = pi == 0, eE = pi == PX - 1, eS = pj == 0, eN = pj == PY - 1;
+    const int ncol = L.ncol, nz = L.nz;
+    const int64_t nv = L.nvp;
+    x += rhs * nv;
+    y += rhs * nv;
+    if (DOT >= kDotWY) w += rhs * nv;
+    const T* khN = L.kh + nv;
+    const int ob = tile_base(c, nz);
+    // neighbours in the order of the nbr table (E, W, N, S); only the edge
+    // columns look theirs up
+    int nb[4] = {0, 0, 0, 0};
+    uint32_t fW = 0, fS = 0;
+    if (eE) nb[0] = tile_base(L.nbr[0 * ncol + c], nz);
+    if (eW) {
+        nb[1] = tile_base(L.nbr[1 * ncol + c], nz);
+        fW = L.fface[c];
+    }
+    if (eN) nb[2] = tile_base(L.nbr[2 * ncol + c], nz);
+    if (eS) {
+        nb[3] = tile_base(L.nbr[3 * ncol + c], nz);
+        fS = L.fface[ncol + c];
+    }
+    const bool edge[4] = {eE, eW, eN, eS};
+    const int k0 = kc * KC;
+    T xc[KC + 2], kvv[KC + 1], dl[KC], xn[KC][4], kh[KC][4];
+#pragma unroll
+    for (int j = 0; j < KC + 2; ++j) {
+        const int k = k0 - 1 + j;
+        xc[j] = (k >= 0 && k < nz) ? x[ob + kTile * k] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < KC + 1; ++j) {
+        const int k = k0 - 1 + j;
+        kvv[j] = (k >= 0 && k < nz) ? L.kv[ob + kTile * k] : T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        const int k = k0 + j;
+        dl[j] = T(0);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) xn[j][d] = kh[j][d] = T(0);
+        if (k < nz) {
+            const int o = ob + kTile * k;
+            if constexpr (NTS) dl[j] = __builtin_nontemporal_load(L.dl + o);
+            else dl[j] = L.dl[o];
+            kh[j][0] = L.kh[o];
+            kh[j][2] = khN[o];
+#pragma unroll
+            for (int d = 0; d < 4; ++d)
+                if (edge[d]) xn[j][d] = x[nb[d] + kTile * k];
+            if (eW) kh[j][1] = L.kh[fW + uint32_t(kTile * k)];
+            if (eS) kh[j][3] = L.kh[fS + uint32_t(kTile * k)];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        lx[j][t] = xc[j + 1];
+        lfe[j][t] = kh[j][0];
+        lfn[j][t] = kh[j][2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        if (!eE) xn[j][0] = lx[j][t + 1];
+        if (!eW) {
+            xn[j][1] = lx[j][t - 1];
+            kh[j][1] = lfe[j][t - 1];
+        }
+        if (!eN) xn[j][2] = lx[j][t + PX];
+        if (!eS) {
+            xn[j][3] = lx[j][t - PX];
+            kh[j][3] = lfn[j][t - PX];
+        }
+    }
+    double acc = 0.0, acc2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < KC; ++j) {
+        const int k = k0 + j;
+        if (k < nz) {
+            const T xo = xc[j + 1];
+            T v = dl[j] * xo;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
+            v += kvv[j + 1] * (xo - xc[j + 2]);
+            v += kvv[j] * (xo - xc[j]);
+            if constexpr (NTS) __builtin_nontemporal_store(v, y + ob + kTile * k);
+            else y[ob + kTile * k] = v;
+            if (DOT == kDotXY) acc += double(xo) * double(v);
+            if (DOT >= kDotWY) acc += double(w[ob + kTile * k]) * double(v);
+            if (DOT == kDotWYYY) acc2 += double(v) * double(v);
+        }
+    }
+    if (DOT != kDotNone) {
+        const double s = block_sum(acc, sh);
+        double s2 = 0.0;
+        if (DOT == kDotWYYY) {
+            __syncthreads();
+            s2 = block_sum(acc2, sh);
+        }
+        store_partial(st, rhs, rest, s, s2, DOT == kDotWYYY);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Residual and restriction fused (Algorithm 1): bc[k][C] = sum over the four
 // children ch of C of (b - H x)[k][ch]. The sum has no averaging factor:

@@ -58,6 +58,29 @@ def test_bicgstab_matches_oracle(L, prm, rtol):
     assert true <= rtol * 1.05 + 1e-13
 
 
+@pytest.mark.parametrize("N,cg", [(64, "bicgstab"), (32, "bicgstab"), (64, "standard"),
+                                  (64, "flexible")])
+def test_patch_staged_apply_matches_oracle(N, cg):
+    """Panels whose width is a multiple of 64 (32) take the operator apply
+    staged through LDS in 64 x 4 (32 x 8) column patches, with every dot
+    product it carries ((r0, v) and (t, s), (t, t) in BiCGStab, p.q in CG)."""
+    print(f"patch-staged apply N={N} {cg}", flush=True)
+    nz, L, rtol = 6, 3, 1e-8
+    hier, op = _setup(N, nz, L, w_v=1000.0, graded=True, cg=cg)
+    b = workloads.rhs(N, nz)[0]
+    method = "bicgstab" if cg == "bicgstab" else "cg"
+    ref = krylov.solve(hier, b, rtol=rtol, method=method, flexible=cg == "flexible")
+    res = op.solve(torch.from_numpy(b).cuda(), rtol=rtol)
+    print(f"  iterations {res.iters[0]} (oracle {ref.iters}), solution "
+          f"{_relnorm(res.x, ref.x):.2e}", flush=True)
+    assert ref.converged and res.converged
+    assert abs(res.iters[0] - ref.iters) <= 1
+    if res.iters[0] == ref.iters:
+        assert _relnorm(res.x, ref.x) <= 1e-8
+    true = np.linalg.norm(b - hier.apply(0, res.x.cpu().numpy())) / np.linalg.norm(b)
+    assert true <= rtol * 1.05 + 1e-13
+
+
 def test_bicgstab_fp32_preconditioner():
     """Float32 V-cycle inside the float64 BiCGStab: same iterations as the float64
     oracle +-1 and the float64 true residual meets the tolerance."""
