@@ -520,7 +520,11 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
                  k_resid_restrict<T, true, true, false, kSym, true>);
         else go(k_resid_restrict<T, true, false>);
     } else if (h->nine) {
-        if (pair)
+        if (pair && c.N % 32 == 0)
+            pick(k_resid_restrict_lds<T, false, 32, true>, k_resid_restrict_lds<T, true, 32, true>);
+        else if (pair && c.N % 16 == 0)
+            pick(k_resid_restrict_lds<T, false, 16, true>, k_resid_restrict_lds<T, true, 16, true>);
+        else if (pair)
             pick(k_resid_restrict<T, false, true, true>,
                  k_resid_restrict<T, false, true, true, kSym, true>);
         else go(k_resid_restrict<T, false, false, true>);
@@ -576,6 +580,30 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
                 default: go(k_apply<T, kDotNone, kApplyChunk, false, kRowW>); break;
             }
         }
+    } else if (v.N % kTile == 0) {
+        // the panels tile into patches of 64 x 4 (else 32 x 8) columns:
+        // neighbours' values through LDS (7-point and 9-cell stencils)
+        auto patch = [&](auto nts, auto px, auto k2) {
+            constexpr bool NT = decltype(nts)::value;
+            constexpr int PX = decltype(px)::value;
+            constexpr bool K2 = decltype(k2)::value;
+            switch (dot) {
+                case kDotXY: go(k_apply_lds<T, kDotXY, kApplyChunk, NT, PX, K2>); break;
+                case kDotWY: go(k_apply_lds<T, kDotWY, kApplyChunk, NT, PX, K2>); break;
+                case kDotWYYY: go(k_apply_lds<T, kDotWYYY, kApplyChunk, NT, PX, K2>); break;
+                default: go(k_apply_lds<T, kDotNone, kApplyChunk, NT, PX, K2>); break;
+            }
+        };
+        auto by_width = [&](auto nts, auto k2) {
+            if (v.N % 64 == 0) patch(nts, std::integral_constant<int, 64>{}, k2);
+            else patch(nts, std::integral_constant<int, 32>{}, k2);
+        };
+        auto by_stencil = [&](auto nts) {
+            if (h->nine) by_width(nts, std::true_type{});
+            else by_width(nts, std::false_type{});
+        };
+        if (streams_past_cache(h, l, batch, sizeof(T))) by_stencil(std::true_type{});
+        else by_stencil(std::false_type{});
     } else if (h->nine) {
         switch (dot) {
             case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, true>); break;
@@ -583,24 +611,6 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
             case kDotWYYY: go(k_apply<T, kDotWYYY, kApplyChunk, true>); break;
             default: go(k_apply<T, kDotNone, kApplyChunk, true>); break;
         }
-    } else if (v.N % kTile == 0) {
-        // the panels tile into patches of 64 x 4 (else 32 x 8) columns:
-        // neighbours' values through LDS
-        auto patch = [&](auto nts, auto px) {
-            constexpr bool NT = decltype(nts)::value;
-            constexpr int PX = decltype(px)::value;
-            switch (dot) {
-                case kDotXY: go(k_apply_lds<T, kDotXY, kApplyChunk, NT, PX>); break;
-                case kDotWY: go(k_apply_lds<T, kDotWY, kApplyChunk, NT, PX>); break;
-                case kDotWYYY: go(k_apply_lds<T, kDotWYYY, kApplyChunk, NT, PX>); break;
-                default: go(k_apply_lds<T, kDotNone, kApplyChunk, NT, PX>); break;
-            }
-        };
-        using P64 = std::integral_constant<int, 64>;
-        using P32 = std::integral_constant<int, 32>;
-        const bool nt = streams_past_cache(h, l, batch, sizeof(T));
-        if (v.N % 64 == 0) nt ? patch(std::true_type{}, P64{}) : patch(std::false_type{}, P64{});
-        else nt ? patch(std::true_type{}, P32{}) : patch(std::false_type{}, P32{});
     } else if (streams_past_cache(h, l, batch, sizeof(T))) {
         switch (dot) {
             case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, false, kSym, true>); break;

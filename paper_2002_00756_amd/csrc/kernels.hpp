@@ -783,7 +783,7 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
 // 32 x 8 (patches walked column by column: 168 us). y is computed by the same
 // expression as in k_apply and is identical; the partial sums of the dot
 // products follow the patches.
-template <typename T, int DOT, int KC, bool NTS, int PX>
+template <typename T, int DOT, int KC, bool NTS, int PX, bool K2 = false>
 __global__ void __launch_bounds__(kBlock)
 k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
             int batch, int nkc, CgState st, const int* __restrict__ active, int rev) {
@@ -837,6 +837,18 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
         const int k = k0 - 1 + j;
         kvv[j] = (k >= 0 && k < nz) ? L.kv[ob + kTile * k] : T(0);
     }
+    // 9-cell: x at k0-2 and k0+KC+1 (xc holds k0-1 .. k0+KC), kv2 at
+    // k0-2 .. k0+KC-1
+    T xlo = T(0), xhi = T(0), k2v[KC + 2];
+    if constexpr (K2) {
+        if (k0 >= 2) xlo = x[ob + kTile * (k0 - 2)];
+        if (k0 + KC + 1 < nz) xhi = x[ob + kTile * (k0 + KC + 1)];
+#pragma unroll
+        for (int j = 0; j < KC + 2; ++j) {
+            const int k = k0 - 2 + j;
+            k2v[j] = (k >= 0 && k < nz) ? L.kv2[ob + kTile * k] : T(0);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
         const int k = k0 + j;
@@ -887,6 +899,12 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
             for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
             v += kvv[j + 1] * (xo - xc[j + 2]);
             v += kvv[j] * (xo - xc[j]);
+            if constexpr (K2) {
+                const T xm2 = j >= 1 ? xc[j - 1] : xlo;
+                const T xp2 = j + 3 <= KC + 1 ? xc[j + 3] : xhi;
+                v += k2v[j + 2] * (xo - xp2);
+                v += k2v[j] * (xo - xm2);
+            }
             if constexpr (NTS) __builtin_nontemporal_store(v, y + ob + kTile * k);
             else y[ob + kTile * k] = v;
             if (DOT == kDotXY) acc += double(xo) * double(v);
@@ -1167,7 +1185,7 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
 // float32, 88.7 us (k_resid_restrict) -> 76.6 (16 x 16) -> 71.8 us (32 x 8).
 // Same arithmetic, in the same order, as k_resid_restrict: the results are
 // identical.
-template <typename T, bool NTS, int PX>
+template <typename T, bool NTS, int PX, bool K2 = false>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
                      const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
@@ -1235,6 +1253,23 @@ k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol
     }
     load_pair<T, true>(x, kTile * k0 + cb[0], xo[0], xo[1]);
     load_pair<T, true>(x, kTile * k0 + cb[2], xo[2], xo[3]);
+    // 9-cell: window x[k-2], kv2[k-2], kv2[k-1] of the four children
+    T xm2[4] = {T(0), T(0), T(0), T(0)}, k2m2[4] = {T(0), T(0), T(0), T(0)};
+    T k2m1[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (K2) {
+        if (k0 >= 2) {
+            const int r2 = kTile * (k0 - 2);
+            load_pair<T, true>(x, r2 + cb[0], xm2[0], xm2[1]);
+            load_pair<T, true>(x, r2 + cb[2], xm2[2], xm2[3]);
+            load_pair<T, true>(F.kv2, r2 + cb[0], k2m2[0], k2m2[1]);
+            load_pair<T, true>(F.kv2, r2 + cb[2], k2m2[2], k2m2[3]);
+        }
+        if (k0 >= 1) {
+            const int r1 = kTile * (k0 - 1);
+            load_pair<T, true>(F.kv2, r1 + cb[0], k2m1[0], k2m1[1]);
+            load_pair<T, true>(F.kv2, r1 + cb[2], k2m1[2], k2m1[3]);
+        }
+    }
     for (int k = k0; k < k1; ++k) {
         const int r = kTile * k, buf = k & 1;
         T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8], unused;
@@ -1300,9 +1335,27 @@ k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol
         }
 #pragma unroll
         for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
+        T k2[4] = {T(0), T(0), T(0), T(0)};
+        if constexpr (K2) {
+            T xp2[4] = {T(0), T(0), T(0), T(0)};
+            if (k + 2 < nz) {
+                load_pair<T, true>(x, r + 2 * kTile + cb[0], xp2[0], xp2[1]);
+                load_pair<T, true>(x, r + 2 * kTile + cb[2], xp2[2], xp2[3]);
+            }
+            load_pair<T, true>(F.kv2, r + cb[0], k2[0], k2[1]);
+            load_pair<T, true>(F.kv2, r + cb[2], k2[2], k2[3]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc -= k2[s] * (xo[s] - xp2[s]) + k2m2[s] * (xo[s] - xm2[s]);
+        }
         bc[r] = acc;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
+            if constexpr (K2) {
+                xm2[s] = xdn[s];
+                k2m2[s] = k2m1[s];
+                k2m1[s] = k2[s];
+            }
             xdn[s] = xo[s];
             xo[s] = xup[s];
             kvdn[s] = vkv[s];

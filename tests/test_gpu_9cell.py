@@ -42,6 +42,11 @@ CASES = [
     (24, 30, 4, 1.0, 1000.0, 10.0, True),
     (6, 70, 2, 1.0, 1000.0, 10.0, True),
     (16, 120, 5, 2.0, 10.0, 3.0, False),
+    # the apply and the residual restriction staged through LDS in patches
+    # (panel widths 32 and 64: column patches 32 x 8 and 64 x 4; coarse
+    # patches 16 x 16 and 32 x 8)
+    (32, 8, 3, 1.0, 1000.0, 10.0, True),
+    (64, 6, 3, 1.0, 100.0, 3.0, False),
 ]
 
 
@@ -79,6 +84,21 @@ def test_solve_matches_oracle(cg, precision):
         assert res.converged and abs(res.iters[0] - ref.iters) <= 1, (res.iters, ref.iters)
         true = np.linalg.norm(b - hier.apply(0, res.x.cpu().numpy())) / np.linalg.norm(b)
         assert true <= rtol * 1.05 + 1e-13
+
+
+@pytest.mark.parametrize("cg", ["standard", "bicgstab"])
+def test_patch_paths_solve_matches_oracle(cg):
+    """The patch-staged apply with every dot product it carries, in CG and
+    BiCGStab, on a 9-cell operator whose panel width is a multiple of 64."""
+    print(f"9-cell patch paths {cg}", flush=True)
+    N, nz, L = 64, 6, 3
+    hier, op = _setup(N, nz, L, w_v=1000.0, w_v2=10.0, graded=True, cg=cg)
+    b = workloads.rhs(N, nz)[0]
+    ref = krylov.solve(hier, b, rtol=1e-8, method="bicgstab" if cg == "bicgstab" else "cg")
+    res = op.solve(torch.from_numpy(b).cuda(), rtol=1e-8)
+    assert res.converged and abs(res.iters[0] - ref.iters) <= 1, (res.iters, ref.iters)
+    true = np.linalg.norm(b - hier.apply(0, res.x.cpu().numpy())) / np.linalg.norm(b)
+    assert true <= 1e-8 * 1.05 + 1e-13
 
 
 def test_face_grad_with_kv2():
