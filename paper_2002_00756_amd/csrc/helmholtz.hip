@@ -529,12 +529,24 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
                  k_resid_restrict<T, false, true, true, kSym, true>);
         else go(k_resid_restrict<T, false, false, true>);
     } else if (h->weighted && h->adj) {
-        if (pair)
+        if (pair && c.N % 32 == 0)
+            pick(k_resid_restrict_lds<T, false, 32, false, kRowWT>,
+                 k_resid_restrict_lds<T, true, 32, false, kRowWT>);
+        else if (pair && c.N % 16 == 0)
+            pick(k_resid_restrict_lds<T, false, 16, false, kRowWT>,
+                 k_resid_restrict_lds<T, true, 16, false, kRowWT>);
+        else if (pair)
             pick(k_resid_restrict<T, false, true, false, kRowWT>,
                  k_resid_restrict<T, false, true, false, kRowWT, true>);
         else go(k_resid_restrict<T, false, false, false, kRowWT>);
     } else if (h->weighted) {
-        if (pair)
+        if (pair && c.N % 32 == 0)
+            pick(k_resid_restrict_lds<T, false, 32, false, kRowW>,
+                 k_resid_restrict_lds<T, true, 32, false, kRowW>);
+        else if (pair && c.N % 16 == 0)
+            pick(k_resid_restrict_lds<T, false, 16, false, kRowW>,
+                 k_resid_restrict_lds<T, true, 16, false, kRowW>);
+        else if (pair)
             pick(k_resid_restrict<T, false, true, false, kRowW>,
                  k_resid_restrict<T, false, true, false, kRowW, true>);
         else go(k_resid_restrict<T, false, false, false, kRowW>);
@@ -564,7 +576,38 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
         hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), x, y, w, batch, nkc,
                            cg_state(h), active, rev);
     };
-    if (h->weighted) {
+    if (v.N % kTile == 0) {
+        // the panels tile into patches of 64 x 4 (else 32 x 8) columns:
+        // neighbours' values through LDS (every operator form); the
+        // weighted operator keeps plain loads, as before
+        auto patch = [&](auto nts, auto px, auto k2, auto sc) {
+            constexpr bool NT = decltype(nts)::value;
+            constexpr int PX = decltype(px)::value;
+            constexpr bool K2 = decltype(k2)::value;
+            constexpr int SC = decltype(sc)::value;
+            switch (dot) {
+                case kDotXY: go(k_apply_lds<T, kDotXY, kApplyChunk, NT, PX, K2, SC>); break;
+                case kDotWY: go(k_apply_lds<T, kDotWY, kApplyChunk, NT, PX, K2, SC>); break;
+                case kDotWYYY: go(k_apply_lds<T, kDotWYYY, kApplyChunk, NT, PX, K2, SC>); break;
+                default: go(k_apply_lds<T, kDotNone, kApplyChunk, NT, PX, K2, SC>); break;
+            }
+        };
+        auto by_width = [&](auto nts, auto k2, auto sc) {
+            if (v.N % 64 == 0) patch(nts, std::integral_constant<int, 64>{}, k2, sc);
+            else patch(nts, std::integral_constant<int, 32>{}, k2, sc);
+        };
+        using Sym = std::integral_constant<int, kSym>;
+        if (h->weighted && h->adj)
+            by_width(std::false_type{}, std::false_type{}, std::integral_constant<int, kRowWT>{});
+        else if (h->weighted)
+            by_width(std::false_type{}, std::false_type{}, std::integral_constant<int, kRowW>{});
+        else if (streams_past_cache(h, l, batch, sizeof(T)))
+            h->nine ? by_width(std::true_type{}, std::true_type{}, Sym{})
+                    : by_width(std::true_type{}, std::false_type{}, Sym{});
+        else
+            h->nine ? by_width(std::false_type{}, std::true_type{}, Sym{})
+                    : by_width(std::false_type{}, std::false_type{}, Sym{});
+    } else if (h->weighted) {
         if (h->adj) {
             switch (dot) {
                 case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, false, kRowWT>); break;
@@ -580,30 +623,6 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
                 default: go(k_apply<T, kDotNone, kApplyChunk, false, kRowW>); break;
             }
         }
-    } else if (v.N % kTile == 0) {
-        // the panels tile into patches of 64 x 4 (else 32 x 8) columns:
-        // neighbours' values through LDS (7-point and 9-cell stencils)
-        auto patch = [&](auto nts, auto px, auto k2) {
-            constexpr bool NT = decltype(nts)::value;
-            constexpr int PX = decltype(px)::value;
-            constexpr bool K2 = decltype(k2)::value;
-            switch (dot) {
-                case kDotXY: go(k_apply_lds<T, kDotXY, kApplyChunk, NT, PX, K2>); break;
-                case kDotWY: go(k_apply_lds<T, kDotWY, kApplyChunk, NT, PX, K2>); break;
-                case kDotWYYY: go(k_apply_lds<T, kDotWYYY, kApplyChunk, NT, PX, K2>); break;
-                default: go(k_apply_lds<T, kDotNone, kApplyChunk, NT, PX, K2>); break;
-            }
-        };
-        auto by_width = [&](auto nts, auto k2) {
-            if (v.N % 64 == 0) patch(nts, std::integral_constant<int, 64>{}, k2);
-            else patch(nts, std::integral_constant<int, 32>{}, k2);
-        };
-        auto by_stencil = [&](auto nts) {
-            if (h->nine) by_width(nts, std::true_type{});
-            else by_width(nts, std::false_type{});
-        };
-        if (streams_past_cache(h, l, batch, sizeof(T))) by_stencil(std::true_type{});
-        else by_stencil(std::false_type{});
     } else if (h->nine) {
         switch (dot) {
             case kDotXY: go(k_apply<T, kDotXY, kApplyChunk, true>); break;

@@ -783,13 +783,15 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
 // 32 x 8 (patches walked column by column: 168 us). y is computed by the same
 // expression as in k_apply and is identical; the partial sums of the dot
 // products follow the patches.
-template <typename T, int DOT, int KC, bool NTS, int PX, bool K2 = false>
+template <typename T, int DOT, int KC, bool NTS, int PX, bool K2 = false, int SC = kSym>
 __global__ void __launch_bounds__(kBlock)
 k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
             int batch, int nkc, CgState st, const int* __restrict__ active, int rev) {
     constexpr int PY = kBlock / PX;
     static_assert(PX * PY == kBlock && PX % kTile == 0, "patch rows are whole storage tiles");
-    __shared__ T lx[KC][kBlock];   // x at k0 .. k0 + KC - 1
+    static_assert(!(K2 && SC != kSym), "the weighted operator has the 7-point stencil");
+    // x at k0 .. k0 + KC - 1 (H^T: u = s x, the values its fluxes act on)
+    __shared__ T lx[KC][kBlock];
     __shared__ T lfe[KC][kBlock];  // E faces
     __shared__ T lfn[KC][kBlock];  // N faces
     __shared__ double sh[kBlock / 64];
@@ -826,11 +828,15 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
     }
     const bool edge[4] = {eE, eW, eN, eS};
     const int k0 = kc * KC;
+    // xn: the neighbours' x (H^T: s x, as the neighbour forms it)
     T xc[KC + 2], kvv[KC + 1], dl[KC], xn[KC][4], kh[KC][4];
+    T sc[KC + 2];  // weighted operator: own weights at k0-1 .. k0+KC (as xc)
 #pragma unroll
     for (int j = 0; j < KC + 2; ++j) {
         const int k = k0 - 1 + j;
         xc[j] = (k >= 0 && k < nz) ? x[ob + kTile * k] : T(0);
+        sc[j] = T(1);
+        if (SC != kSym && k >= 0 && k < nz) sc[j] = L.s[ob + kTile * k];
     }
 #pragma unroll
     for (int j = 0; j < KC + 1; ++j) {
@@ -863,14 +869,17 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
             kh[j][2] = khN[o];
 #pragma unroll
             for (int d = 0; d < 4; ++d)
-                if (edge[d]) xn[j][d] = x[nb[d] + kTile * k];
+                if (edge[d]) {
+                    xn[j][d] = x[nb[d] + kTile * k];
+                    if constexpr (SC == kRowWT) xn[j][d] = L.s[nb[d] + kTile * k] * xn[j][d];
+                }
             if (eW) kh[j][1] = L.kh[fW + uint32_t(kTile * k)];
             if (eS) kh[j][3] = L.kh[fS + uint32_t(kTile * k)];
         }
     }
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
-        lx[j][t] = xc[j + 1];
+        lx[j][t] = SC == kRowWT ? sc[j + 1] * xc[j + 1] : xc[j + 1];
         lfe[j][t] = kh[j][0];
         lfn[j][t] = kh[j][2];
     }
@@ -895,10 +904,27 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
         if (k < nz) {
             const T xo = xc[j + 1];
             T v = dl[j] * xo;
+            if constexpr (SC == kRowWT) {
+                // H^T x = delta x + L (s x)
+                const T uo = sc[j + 1] * xo;
 #pragma unroll
-            for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
-            v += kvv[j + 1] * (xo - xc[j + 2]);
-            v += kvv[j] * (xo - xc[j]);
+                for (int d = 0; d < 4; ++d) v += kh[j][d] * (uo - xn[j][d]);
+                v += kvv[j + 1] * (uo - sc[j + 2] * xc[j + 2]);
+                v += kvv[j] * (uo - sc[j] * xc[j]);
+            } else if constexpr (SC == kRowW) {
+                // H x = delta x + s (L x)
+                T f = T(0);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) f += kh[j][d] * (xo - xn[j][d]);
+                f += kvv[j + 1] * (xo - xc[j + 2]);
+                f += kvv[j] * (xo - xc[j]);
+                v += sc[j + 1] * f;
+            } else {
+#pragma unroll
+                for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
+                v += kvv[j + 1] * (xo - xc[j + 2]);
+                v += kvv[j] * (xo - xc[j]);
+            }
             if constexpr (K2) {
                 const T xm2 = j >= 1 ? xc[j - 1] : xlo;
                 const T xp2 = j + 3 <= KC + 1 ? xc[j + 3] : xhi;
@@ -1185,13 +1211,15 @@ k_resid_restrict(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, 
 // float32, 88.7 us (k_resid_restrict) -> 76.6 (16 x 16) -> 71.8 us (32 x 8).
 // Same arithmetic, in the same order, as k_resid_restrict: the results are
 // identical.
-template <typename T, bool NTS, int PX, bool K2 = false>
+template <typename T, bool NTS, int PX, bool K2 = false, int SC = kSym>
 __global__ void __launch_bounds__(kBlock)
 k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol_c, int nvp_c,
                      const T* __restrict__ b, const T* __restrict__ x, T* __restrict__ bc,
                      int batch, int kchunk, int nkc, const int* __restrict__ active, int rev) {
-    // [level parity][value][thread]: x of children 00, 10, 01, 11; then the E
-    // faces of 10, 11 and the N faces of 01, 11
+    // [level parity][value][thread]: x of children 00, 10, 01, 11 (H^T:
+    // u = s x, the values its fluxes act on); then the E faces of 10, 11 and
+    // the N faces of 01, 11
+    static_assert(!(K2 && SC != kSym), "the weighted operator has the 7-point stencil");
     __shared__ T lx[2][4][kBlock];
     __shared__ T lf[2][4][kBlock];
     constexpr int PY = kBlock / PX;
@@ -1243,16 +1271,31 @@ k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol
         out[7] = tile_base(F.nbr[2 * ncol + ch[3]], nz);
     }
     const int k0 = kc * kchunk, k1 = min(nz, k0 + kchunk);
+    // H^T: the flux terms act on u = s x, so every x below but the one of
+    // the delta term (xr) is multiplied by its weight
+    auto su = [&](T& v0, T& v1, int off) {
+        if constexpr (SC == kRowWT) {
+            T w0, w1;
+            load_pair<T, true>(F.s, off, w0, w1);
+            v0 *= w0;
+            v1 *= w1;
+        }
+    };
     T xdn[4] = {T(0), T(0), T(0), T(0)}, xo[4], kvdn[4] = {T(0), T(0), T(0), T(0)};
     if (k0 > 0) {
         const int rdn = kTile * (k0 - 1);
         load_pair<T, true>(x, rdn + cb[0], xdn[0], xdn[1]);
         load_pair<T, true>(x, rdn + cb[2], xdn[2], xdn[3]);
+        su(xdn[0], xdn[1], rdn + cb[0]);
+        su(xdn[2], xdn[3], rdn + cb[2]);
         load_pair<T, true>(F.kv, rdn + cb[0], kvdn[0], kvdn[1]);
         load_pair<T, true>(F.kv, rdn + cb[2], kvdn[2], kvdn[3]);
     }
     load_pair<T, true>(x, kTile * k0 + cb[0], xo[0], xo[1]);
     load_pair<T, true>(x, kTile * k0 + cb[2], xo[2], xo[3]);
+    T xr[4] = {xo[0], xo[1], xo[2], xo[3]};
+    su(xo[0], xo[1], kTile * k0 + cb[0]);
+    su(xo[2], xo[3], kTile * k0 + cb[2]);
     // 9-cell: window x[k-2], kv2[k-2], kv2[k-1] of the four children
     T xm2[4] = {T(0), T(0), T(0), T(0)}, k2m2[4] = {T(0), T(0), T(0), T(0)};
     T k2m1[4] = {T(0), T(0), T(0), T(0)};
@@ -1272,10 +1315,17 @@ k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol
     }
     for (int k = k0; k < k1; ++k) {
         const int r = kTile * k, buf = k & 1;
-        T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8], unused;
+        T xup[4] = {T(0), T(0), T(0), T(0)}, vb[4], vd[4], vkv[4], vxo[8], vk[8], iE[2];
+        T xupr[4] = {T(0), T(0), T(0), T(0)};  // H^T: raw x at k+1
         if (k + 1 < nz) {
             load_pair<T, true>(x, r + kTile + cb[0], xup[0], xup[1]);
             load_pair<T, true>(x, r + kTile + cb[2], xup[2], xup[3]);
+            if constexpr (SC == kRowWT) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) xupr[s] = xup[s];
+                su(xup[0], xup[1], r + kTile + cb[0]);
+                su(xup[2], xup[3], r + kTile + cb[2]);
+            }
         }
         load_once(b, r + cb[0], vb[0], vb[1]);
         load_once(b, r + cb[2], vb[2], vb[3]);
@@ -1283,25 +1333,30 @@ k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol
         load_once(F.dl, r + cb[2], vd[2], vd[3]);
         load_pair<T, true>(F.kv, r + cb[0], vkv[0], vkv[1]);
         load_pair<T, true>(F.kv, r + cb[2], vkv[2], vkv[3]);
-        // own faces: E of 10 and 11 (the E of 00, 01 is between siblings), N of 01, 11
-        load_pair<T, true>(F.kh, r + cb[0], unused, vk[2]);
-        load_pair<T, true>(F.kh, r + cb[2], unused, vk[6]);
+        // own faces: E of 10 and 11 (the E of 00, 01 is between siblings:
+        // iE, used by H only), N of 01, 11
+        load_pair<T, true>(F.kh, r + cb[0], iE[0], vk[2]);
+        load_pair<T, true>(F.kh, r + cb[2], iE[1], vk[6]);
         load_pair<T, true>(F.kh + nv, r + cb[2], vk[5], vk[7]);
+        auto outer = [&](int f) {
+            vxo[f] = x[out[f] + r];
+            if constexpr (SC == kRowWT) vxo[f] *= F.s[out[f] + r];
+        };
         if (eW) {
-            vxo[0] = x[out[0] + r]; vk[0] = F.kh[fc[0] + uint32_t(r)];
-            vxo[4] = x[out[4] + r]; vk[4] = F.kh[fc[4] + uint32_t(r)];
+            outer(0); vk[0] = F.kh[fc[0] + uint32_t(r)];
+            outer(4); vk[4] = F.kh[fc[4] + uint32_t(r)];
         }
         if (eE) {
-            vxo[2] = x[out[2] + r];
-            vxo[6] = x[out[6] + r];
+            outer(2);
+            outer(6);
         }
         if (eS) {
-            vxo[1] = x[out[1] + r]; vk[1] = F.kh[fc[1] + uint32_t(r)];
-            vxo[3] = x[out[3] + r]; vk[3] = F.kh[fc[3] + uint32_t(r)];
+            outer(1); vk[1] = F.kh[fc[1] + uint32_t(r)];
+            outer(3); vk[3] = F.kh[fc[3] + uint32_t(r)];
         }
         if (eN) {
-            vxo[5] = x[out[5] + r];
-            vxo[7] = x[out[7] + r];
+            outer(5);
+            outer(7);
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s) lx[buf][s][t] = xo[s];
@@ -1328,13 +1383,35 @@ k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol
             vxo[7] = lx[buf][1][t + PX];
         }
         T acc = ((vb[0] + vb[1]) + vb[2]) + vb[3];
+        if constexpr (SC == kRowW) {
+            // each child's flux row, with the four faces between siblings:
+            // c00|c10 and c01|c11 (E faces of c00, c01), c00|c01 and c10|c11
+            // (N faces of c00, c10)
+            T sw[4], iN0, iN1;
+            load_pair<T, true>(F.s, r + cb[0], sw[0], sw[1]);
+            load_pair<T, true>(F.s, r + cb[2], sw[2], sw[3]);
+            load_pair<T, true>(F.kh + nv, r + cb[0], iN0, iN1);
+            T Lr[4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            acc -= vd[s] * xo[s];
-            acc -= vkv[s] * (xo[s] - xup[s]) + kvdn[s] * (xo[s] - xdn[s]);
+            for (int q = 0; q < 4; ++q)
+                Lr[q] = vkv[q] * (xo[q] - xup[q]) + kvdn[q] * (xo[q] - xdn[q]);
+#pragma unroll
+            for (int f = 0; f < 8; ++f) Lr[f >> 1] += vk[f] * (xo[f >> 1] - vxo[f]);
+            Lr[0] += iE[0] * (xo[0] - xo[1]) + iN0 * (xo[0] - xo[2]);
+            Lr[1] += iE[0] * (xo[1] - xo[0]) + iN1 * (xo[1] - xo[3]);
+            Lr[2] += iE[1] * (xo[2] - xo[3]) + iN0 * (xo[2] - xo[0]);
+            Lr[3] += iE[1] * (xo[3] - xo[2]) + iN1 * (xo[3] - xo[1]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc -= vd[q] * xo[q] + sw[q] * Lr[q];
+        } else {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                acc -= vd[s] * (SC == kRowWT ? xr[s] : xo[s]);
+                acc -= vkv[s] * (xo[s] - xup[s]) + kvdn[s] * (xo[s] - xdn[s]);
+            }
+#pragma unroll
+            for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
         }
-#pragma unroll
-        for (int f = 0; f < 8; ++f) acc -= vk[f] * (xo[f >> 1] - vxo[f]);
         T k2[4] = {T(0), T(0), T(0), T(0)};
         if constexpr (K2) {
             T xp2[4] = {T(0), T(0), T(0), T(0)};
@@ -1358,6 +1435,7 @@ k_resid_restrict_lds(LevelView<T> F, const int32_t* __restrict__ child, int ncol
             }
             xdn[s] = xo[s];
             xo[s] = xup[s];
+            if constexpr (SC == kRowWT) xr[s] = xupr[s];
             kvdn[s] = vkv[s];
         }
     }

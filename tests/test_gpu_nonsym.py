@@ -40,6 +40,10 @@ CASES = [
     (4, 3, 3, 5.0, 1000.0, False),
     (24, 30, 4, 1.0, 1000.0, True),
     (6, 70, 2, 1.0, 1000.0, True),
+    # the apply and the residual restriction staged through LDS in patches
+    # (panel widths 32 and 64), in H and in H^T
+    (32, 8, 3, 1.0, 1000.0, True),
+    (64, 6, 3, 1.0, 100.0, False),
 ]
 
 
@@ -57,8 +61,9 @@ def test_apply_and_vcycles(N, nz, L, w_h, w_v, graded):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_forward_and_adjoint_solves(precision):
-    N, nz, L = 24, 30, 4
+@pytest.mark.parametrize("N,nz,L", [(24, 30, 4), (64, 6, 3)])
+def test_forward_and_adjoint_solves(precision, N, nz, L):
+    print(f"weighted solves N={N} {precision}", flush=True)
     hier, op = _setup(N, nz, L, w_v=1000.0, graded=True, precision=precision)
     ht = hier.transpose()
     b = workloads.rhs(N, nz)[0]
