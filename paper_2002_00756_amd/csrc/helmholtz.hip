@@ -576,37 +576,32 @@ void launch_apply(const helmholtz_s* h, int l, const T* x, T* y, int batch, int 
         hipLaunchKernelGGL(kern, grid, dim3(kBlock), 0, s, view<T>(h, l), x, y, w, batch, nkc,
                            cg_state(h), active, rev);
     };
-    if (v.N % kTile == 0) {
+    if (v.N % kTile == 0 && !h->weighted) {
         // the panels tile into patches of 64 x 4 (else 32 x 8) columns:
-        // neighbours' values through LDS (every operator form); the
-        // weighted operator keeps plain loads, as before
-        auto patch = [&](auto nts, auto px, auto k2, auto sc) {
+        // neighbours' values through LDS (7-point and 9-cell stencils; with
+        // the row-weighted operator it was no faster: each thread's weights
+        // must arrive before it publishes s x, H 227 -> 229, H^T 263 -> 278 us)
+        auto patch = [&](auto nts, auto px, auto k2) {
             constexpr bool NT = decltype(nts)::value;
             constexpr int PX = decltype(px)::value;
             constexpr bool K2 = decltype(k2)::value;
-            constexpr int SC = decltype(sc)::value;
             switch (dot) {
-                case kDotXY: go(k_apply_lds<T, kDotXY, kApplyChunk, NT, PX, K2, SC>); break;
-                case kDotWY: go(k_apply_lds<T, kDotWY, kApplyChunk, NT, PX, K2, SC>); break;
-                case kDotWYYY: go(k_apply_lds<T, kDotWYYY, kApplyChunk, NT, PX, K2, SC>); break;
-                default: go(k_apply_lds<T, kDotNone, kApplyChunk, NT, PX, K2, SC>); break;
+                case kDotXY: go(k_apply_lds<T, kDotXY, kApplyChunk, NT, PX, K2>); break;
+                case kDotWY: go(k_apply_lds<T, kDotWY, kApplyChunk, NT, PX, K2>); break;
+                case kDotWYYY: go(k_apply_lds<T, kDotWYYY, kApplyChunk, NT, PX, K2>); break;
+                default: go(k_apply_lds<T, kDotNone, kApplyChunk, NT, PX, K2>); break;
             }
         };
-        auto by_width = [&](auto nts, auto k2, auto sc) {
-            if (v.N % 64 == 0) patch(nts, std::integral_constant<int, 64>{}, k2, sc);
-            else patch(nts, std::integral_constant<int, 32>{}, k2, sc);
+        auto by_width = [&](auto nts, auto k2) {
+            if (v.N % 64 == 0) patch(nts, std::integral_constant<int, 64>{}, k2);
+            else patch(nts, std::integral_constant<int, 32>{}, k2);
         };
-        using Sym = std::integral_constant<int, kSym>;
-        if (h->weighted && h->adj)
-            by_width(std::false_type{}, std::false_type{}, std::integral_constant<int, kRowWT>{});
-        else if (h->weighted)
-            by_width(std::false_type{}, std::false_type{}, std::integral_constant<int, kRowW>{});
-        else if (streams_past_cache(h, l, batch, sizeof(T)))
-            h->nine ? by_width(std::true_type{}, std::true_type{}, Sym{})
-                    : by_width(std::true_type{}, std::false_type{}, Sym{});
+        if (streams_past_cache(h, l, batch, sizeof(T)))
+            h->nine ? by_width(std::true_type{}, std::true_type{})
+                    : by_width(std::true_type{}, std::false_type{});
         else
-            h->nine ? by_width(std::false_type{}, std::true_type{}, Sym{})
-                    : by_width(std::false_type{}, std::false_type{}, Sym{});
+            h->nine ? by_width(std::false_type{}, std::true_type{})
+                    : by_width(std::false_type{}, std::false_type{});
     } else if (h->weighted) {
         if (h->adj) {
             switch (dot) {

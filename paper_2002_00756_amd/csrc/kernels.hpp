@@ -783,15 +783,13 @@ k_apply(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __r
 // 32 x 8 (patches walked column by column: 168 us). y is computed by the same
 // expression as in k_apply and is identical; the partial sums of the dot
 // products follow the patches.
-template <typename T, int DOT, int KC, bool NTS, int PX, bool K2 = false, int SC = kSym>
+template <typename T, int DOT, int KC, bool NTS, int PX, bool K2 = false>
 __global__ void __launch_bounds__(kBlock)
 k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ w,
             int batch, int nkc, CgState st, const int* __restrict__ active, int rev) {
     constexpr int PY = kBlock / PX;
     static_assert(PX * PY == kBlock && PX % kTile == 0, "patch rows are whole storage tiles");
-    static_assert(!(K2 && SC != kSym), "the weighted operator has the 7-point stencil");
-    // x at k0 .. k0 + KC - 1 (H^T: u = s x, the values its fluxes act on)
-    __shared__ T lx[KC][kBlock];
+    __shared__ T lx[KC][kBlock];   // x at k0 .. k0 + KC - 1
     __shared__ T lfe[KC][kBlock];  // E faces
     __shared__ T lfn[KC][kBlock];  // N faces
     __shared__ double sh[kBlock / 64];
@@ -828,15 +826,11 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
     }
     const bool edge[4] = {eE, eW, eN, eS};
     const int k0 = kc * KC;
-    // xn: the neighbours' x (H^T: s x, as the neighbour forms it)
     T xc[KC + 2], kvv[KC + 1], dl[KC], xn[KC][4], kh[KC][4];
-    T sc[KC + 2];  // weighted operator: own weights at k0-1 .. k0+KC (as xc)
 #pragma unroll
     for (int j = 0; j < KC + 2; ++j) {
         const int k = k0 - 1 + j;
         xc[j] = (k >= 0 && k < nz) ? x[ob + kTile * k] : T(0);
-        sc[j] = T(1);
-        if (SC != kSym && k >= 0 && k < nz) sc[j] = L.s[ob + kTile * k];
     }
 #pragma unroll
     for (int j = 0; j < KC + 1; ++j) {
@@ -869,17 +863,14 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
             kh[j][2] = khN[o];
 #pragma unroll
             for (int d = 0; d < 4; ++d)
-                if (edge[d]) {
-                    xn[j][d] = x[nb[d] + kTile * k];
-                    if constexpr (SC == kRowWT) xn[j][d] = L.s[nb[d] + kTile * k] * xn[j][d];
-                }
+                if (edge[d]) xn[j][d] = x[nb[d] + kTile * k];
             if (eW) kh[j][1] = L.kh[fW + uint32_t(kTile * k)];
             if (eS) kh[j][3] = L.kh[fS + uint32_t(kTile * k)];
         }
     }
 #pragma unroll
     for (int j = 0; j < KC; ++j) {
-        lx[j][t] = SC == kRowWT ? sc[j + 1] * xc[j + 1] : xc[j + 1];
+        lx[j][t] = xc[j + 1];
         lfe[j][t] = kh[j][0];
         lfn[j][t] = kh[j][2];
     }
@@ -904,27 +895,10 @@ k_apply_lds(LevelView<T> L, const T* __restrict__ x, T* __restrict__ y, const T*
         if (k < nz) {
             const T xo = xc[j + 1];
             T v = dl[j] * xo;
-            if constexpr (SC == kRowWT) {
-                // H^T x = delta x + L (s x)
-                const T uo = sc[j + 1] * xo;
 #pragma unroll
-                for (int d = 0; d < 4; ++d) v += kh[j][d] * (uo - xn[j][d]);
-                v += kvv[j + 1] * (uo - sc[j + 2] * xc[j + 2]);
-                v += kvv[j] * (uo - sc[j] * xc[j]);
-            } else if constexpr (SC == kRowW) {
-                // H x = delta x + s (L x)
-                T f = T(0);
-#pragma unroll
-                for (int d = 0; d < 4; ++d) f += kh[j][d] * (xo - xn[j][d]);
-                f += kvv[j + 1] * (xo - xc[j + 2]);
-                f += kvv[j] * (xo - xc[j]);
-                v += sc[j + 1] * f;
-            } else {
-#pragma unroll
-                for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
-                v += kvv[j + 1] * (xo - xc[j + 2]);
-                v += kvv[j] * (xo - xc[j]);
-            }
+            for (int d = 0; d < 4; ++d) v += kh[j][d] * (xo - xn[j][d]);
+            v += kvv[j + 1] * (xo - xc[j + 2]);
+            v += kvv[j] * (xo - xc[j]);
             if constexpr (K2) {
                 const T xm2 = j >= 1 ? xc[j - 1] : xlo;
                 const T xp2 = j + 3 <= KC + 1 ? xc[j + 3] : xhi;
