@@ -26,14 +26,16 @@ def _pair(op, b, rtol, maxiter=200):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("cg", ["standard", "flexible"])
-def test_queued_ahead_matches_in_order(precision, cg):
+@pytest.mark.parametrize("N,nz,L", [(24, 30, 4), (64, 6, 3)])
+def test_queued_ahead_matches_in_order(precision, cg, N, nz, L):
     from paper_2002_00756_amd import Operator
-    print(f"queue ahead {precision} {cg}", flush=True)
-    kh, kv, delta = workloads.coefficients(24, 30, 1.0, 1000.0, True)
-    op = Operator(24, 30, kh, kv, delta, 4, precision=precision, cg=cg, max_batch=3)
-    r = workloads.rhs(24, 30)[0]
+    print(f"queue ahead {precision} {cg} N={N}", flush=True)
+    kh, kv, delta = workloads.coefficients(N, nz, 1.0, 1000.0, True)
+    op = Operator(N, nz, kh, kv, delta, L, precision=precision, cg=cg, max_batch=3)
+    r = workloads.rhs(N, nz)[0]
     # members that converge at different iterations, and one that never starts
-    b = torch.from_numpy(np.stack([r, np.tile(r.mean(axis=0), (30, 1)), np.zeros_like(r)])).cuda()
+    b = torch.from_numpy(np.stack([r, np.tile(r.mean(axis=0), (nz, 1)),
+                                   np.zeros_like(r)])).cuda()
     seen = set()
     for rtol in (0.9, 0.3, 1e-1, 3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8,
                  1e-9, 1e-10):
