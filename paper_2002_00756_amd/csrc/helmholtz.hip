@@ -514,52 +514,38 @@ void launch_resid_restrict(const helmholtz_s* h, int l, const T* b, const T* x, 
         if (nts) go(streamed);
         else go(plain);
     };
+    // each operator form: where the coarse panels tile into patches (32 x 8,
+    // else 16 x 16 coarse cells), the children's values go through LDS
+    // (k_resid_restrict_lds); otherwise the gathering kernel
+    auto form = [&](auto k2, auto sc) {
+        constexpr bool K2 = decltype(k2)::value;
+        constexpr int SC = decltype(sc)::value;
+        if (pair && c.N % 32 == 0)
+            pick(k_resid_restrict_lds<T, false, 32, K2, SC>,
+                 k_resid_restrict_lds<T, true, 32, K2, SC>);
+        else if (pair && c.N % 16 == 0)
+            pick(k_resid_restrict_lds<T, false, 16, K2, SC>,
+                 k_resid_restrict_lds<T, true, 16, K2, SC>);
+        else if (pair)
+            pick(k_resid_restrict<T, false, true, K2, SC>,
+                 k_resid_restrict<T, false, true, K2, SC, true>);
+        else
+            go(k_resid_restrict<T, false, false, K2, SC>);
+    };
+    using Sym = std::integral_constant<int, kSym>;
     if (!x) {
         if (pair)
             pick(k_resid_restrict<T, true, true>,
                  k_resid_restrict<T, true, true, false, kSym, true>);
         else go(k_resid_restrict<T, true, false>);
     } else if (h->nine) {
-        if (pair && c.N % 32 == 0)
-            pick(k_resid_restrict_lds<T, false, 32, true>, k_resid_restrict_lds<T, true, 32, true>);
-        else if (pair && c.N % 16 == 0)
-            pick(k_resid_restrict_lds<T, false, 16, true>, k_resid_restrict_lds<T, true, 16, true>);
-        else if (pair)
-            pick(k_resid_restrict<T, false, true, true>,
-                 k_resid_restrict<T, false, true, true, kSym, true>);
-        else go(k_resid_restrict<T, false, false, true>);
+        form(std::true_type{}, Sym{});
     } else if (h->weighted && h->adj) {
-        if (pair && c.N % 32 == 0)
-            pick(k_resid_restrict_lds<T, false, 32, false, kRowWT>,
-                 k_resid_restrict_lds<T, true, 32, false, kRowWT>);
-        else if (pair && c.N % 16 == 0)
-            pick(k_resid_restrict_lds<T, false, 16, false, kRowWT>,
-                 k_resid_restrict_lds<T, true, 16, false, kRowWT>);
-        else if (pair)
-            pick(k_resid_restrict<T, false, true, false, kRowWT>,
-                 k_resid_restrict<T, false, true, false, kRowWT, true>);
-        else go(k_resid_restrict<T, false, false, false, kRowWT>);
+        form(std::false_type{}, std::integral_constant<int, kRowWT>{});
     } else if (h->weighted) {
-        if (pair && c.N % 32 == 0)
-            pick(k_resid_restrict_lds<T, false, 32, false, kRowW>,
-                 k_resid_restrict_lds<T, true, 32, false, kRowW>);
-        else if (pair && c.N % 16 == 0)
-            pick(k_resid_restrict_lds<T, false, 16, false, kRowW>,
-                 k_resid_restrict_lds<T, true, 16, false, kRowW>);
-        else if (pair)
-            pick(k_resid_restrict<T, false, true, false, kRowW>,
-                 k_resid_restrict<T, false, true, false, kRowW, true>);
-        else go(k_resid_restrict<T, false, false, false, kRowW>);
-    } else if (pair && c.N % 32 == 0) {
-        // the coarse panels tile into patches: children's values through LDS
-        pick(k_resid_restrict_lds<T, false, 32>, k_resid_restrict_lds<T, true, 32>);
-    } else if (pair && c.N % 16 == 0) {
-        pick(k_resid_restrict_lds<T, false, 16>, k_resid_restrict_lds<T, true, 16>);
+        form(std::false_type{}, std::integral_constant<int, kRowW>{});
     } else {
-        if (pair)
-            pick(k_resid_restrict<T, false, true>,
-                 k_resid_restrict<T, false, true, false, kSym, true>);
-        else go(k_resid_restrict<T, false, false>);
+        form(std::false_type{}, Sym{});
     }
 }
 
