@@ -53,6 +53,7 @@ CASES = [
     # patches (coarse panel width 16), 32 x 8 then 16 x 16 (widths 32, 16)
     (32, 8, 3, 1.0, 1000.0, True),
     (64, 6, 3, 1.0, 100.0, False),
+    (64, 1, 2, 1.0, 100.0, False),  # one layer: no vertical couplings
 ]
 
 
