@@ -23,8 +23,9 @@ def _op(N, nz, L, precision, batch):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_noalloc_vcycle_matches_vcycle(precision):
     # first a larger input (C24 x 30, 4 levels, batch 3), then a smaller one
-    # (C12 x 10, 3 levels, batch 1) in the same scratch
-    for N, nz, L, batch, seed in ((24, 30, 4, 3, 21), (12, 10, 3, 1, 22)):
+    # (C12 x 10, 3 levels, batch 1) in the same scratch; then C64 x 6, whose
+    # residual restriction is the patch-staged kernel on scratch buffers
+    for N, nz, L, batch, seed in ((24, 30, 4, 3, 21), (12, 10, 3, 1, 22), (64, 6, 3, 2, 23)):
         print(f"noalloc {precision} C{N}x{nz} L={L} batch={batch}", flush=True)
         op = _op(N, nz, L, precision, batch)
         b = torch.from_numpy(workloads.rhs(N, nz, batch, seed=seed)).cuda()
